@@ -1,0 +1,270 @@
+#!/usr/bin/env python3
+"""Benchmark: CG time-to-solution (mixed precision vs FP64) and Dslash HBM
+bandwidth for the Wilson-Dirac normal equations on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--inner auto|bf16|f16|f32]
+
+Workload: 32^3 x 64 periodic lattice, links exp(i 0.3 H) (H a Gaussian
+combination of Gell-Mann matrices), m = 0.02, one Gaussian complex128
+source; solve D^+D x = D^+b to a true relative residual of 1e-10.
+A step is one complete solve with the mixed-precision reliable-update CG
+(FP32 arithmetic on 16-bit or FP32 storage, FP64 reliable updates every 50
+iterations), inputs resident in HBM. The same solve in plain FP64 CG is timed
+beside it. The roofline object is the packed Wilson stencil in the inner
+storage precision, timed with HIP events on its own stream.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "CG time-to-1e-10 mixed vs FP64; Dslash GB/s & % HBM peak; 32^3x64 lattice"
+HBM_PEAK_GBS = 8000.0
+DIMS = (32, 32, 32, 64)
+MASS = 0.02
+EPS = 0.3
+SEED_U = 200105238
+SEED_B = 200105239
+TOL = 1e-10
+# algorithmic bytes per site of one Wilson application (each link and spinor
+# moved once; 4 links x 9 complex + spinor in + spinor out)
+BYTES_PER_SITE = {"f64": 4 * 9 * 16 + 2 * 192, "f32": 4 * 9 * 8 + 2 * 96, "bf16": 4 * 9 * 4 + 2 * 48,
+                  "f16": 4 * 9 * 4 + 2 * 48 + 2 * 4}
+FLOPS_PER_SITE = 1368
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--inner", default="auto", choices=["auto", "bf16", "f16", "f32"])
+    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--dslash-reps", type=int, default=200)
+    ap.add_argument("--dims", default=",".join(str(d) for d in DIMS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-only", action="store_true", help=argparse.SUPPRESS)
+    return ap.parse_args()
+
+
+# ----------------------------------------------------------- CPU baseline
+
+def cpu_sample(dims):
+    """One FP64 oracle CGNR iteration (D, D^+ and the vector updates) on the
+    full lattice; run in a single-threaded child process."""
+    import fieldgen
+    import oracle
+    U = fieldgen.gauge_field(dims, "near_identity", SEED_U, eps=EPS)
+    b = fieldgen.gaussian_spinor(dims, SEED_B)
+    p = b.copy()
+    r = b.copy()
+    x = np.zeros_like(b)
+    rho = float(np.vdot(r, r).real)
+    t0 = time.perf_counter()
+    t = oracle.wilson_D(U, p, MASS)
+    alpha = rho / float(np.vdot(t, t).real)
+    x += alpha * p
+    q = oracle.wilson_Ddag(U, t, MASS)
+    r -= alpha * q
+    rho2 = float(np.vdot(r, r).real)
+    p = r + (rho2 / rho) * p
+    dt = time.perf_counter() - t0
+    print(json.dumps({"iter_seconds": dt}))
+
+
+def run_cpu_baseline(dims, fp64_iters):
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
+               HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-sample-only", "--dims", ",".join(map(str, dims))]
+    out = subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=900)
+    if out.returncode != 0:
+        raise RuntimeError(out.stderr[-2000:])
+    it = json.loads(out.stdout.strip().splitlines()[-1])["iter_seconds"]
+    return {
+        "value": it * fp64_iters,
+        "unit": "s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"one CGNR iteration (D, D^+, axpys) of the numpy FP64 oracle on the full "
+                   f"{'x'.join(map(str, dims))} lattice took {it:.2f} s on 1 host core "
+                   f"(OMP/OPENBLAS/MKL threads = 1; host has {os.cpu_count()} logical CPUs); "
+                   f"value = that time x the {fp64_iters} iterations of the FP64 solve"),
+        "iter_seconds": it,
+    }
+
+
+# -------------------------------------------------------------------- GPU
+
+def main():
+    args = parse()
+    dims = tuple(int(v) for v in args.dims.split(","))
+    if args.cpu_sample_only:
+        cpu_sample(dims)
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the solver is a single-GPU "
+              "library; multi-GPU sharding is a design note, not an implemented path.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import fieldgen
+    import paper_2001_05218_amd as wd
+
+    dev = torch.device("cuda:0")
+    V = int(np.prod(dims))
+    log(f"generating fields {dims}")
+    t0 = time.time()
+    U = fieldgen.gauge_field(dims, "near_identity", SEED_U, eps=EPS)
+    b = fieldgen.gaussian_spinor(dims, SEED_B)
+    Ut = torch.from_numpy(U).to(dev)
+    bt = torch.from_numpy(b).to(dev)
+    del U
+    log(f"fields ready in {time.time() - t0:.1f} s")
+
+    def solve(inner, ws=None):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x, info = wd.cg_solve(Ut, bt, MASS, tol=TOL, max_iter=20000, inner=inner, reliable_interval=50,
+                              workspace=ws)
+        torch.cuda.synchronize()
+        return x, info, time.perf_counter() - t
+
+    ws = {}
+    for inner in ("f64", "f32", "bf16", "f16"):
+        p, _ = wd.ops.make_params(TOL, 20000, inner, 50, "source")
+        ws[inner] = torch.empty(wd.workspace_bytes(dims, p), dtype=torch.uint8, device=dev)
+        del p
+
+    # candidates for the headline inner precision
+    cands = ["bf16", "f16", "f32"] if args.inner == "auto" else [args.inner]
+    variants = {}
+    for inner in cands:
+        for _ in range(max(1, args.warmup)):
+            x, info, dt = solve(inner, ws[inner])
+        variants[inner] = {"seconds": dt, "iterations": info["iterations"],
+                           "reliable_updates": info["reliable_updates"], "true_rel_res": info["true_rel_res"]}
+        log(f"warmup {inner}: {dt:.3f} s, {info['iterations']} it, {info['reliable_updates']} upd, "
+            f"res {info['true_rel_res']:.2e}")
+    best = min(variants, key=lambda k: variants[k]["seconds"])
+
+    # FP64 reference solve on the same GPU
+    x64, i64, _ = solve("f64", ws["f64"])
+    f64_times = []
+    for _ in range(max(1, args.fp64_steps)):
+        x64, i64, dt = solve("f64", ws["f64"])
+        f64_times.append(dt)
+    fp64 = {"seconds": float(np.median(f64_times)), "iterations": i64["iterations"],
+            "true_rel_res": i64["true_rel_res"]}
+    log(f"fp64: {fp64}")
+
+    # timed region: K full mixed solves
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        x, info = wd.cg_solve(Ut, bt, MASS, tol=TOL, max_iter=20000, inner=best, reliable_interval=50,
+                              workspace=ws[best])
+        infos.append(info)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    per = elapsed / args.steps
+    assert all(i["true_rel_res"] <= TOL for i in infos), infos
+    log(f"mixed {best}: {per:.4f} s per solve")
+
+    # error of the mixed solution against the FP64 solution and a sampled
+    # oracle residual (the oracle evaluates D^+D x site by site)
+    xm = x.cpu().numpy()
+    x64n = x64.cpu().numpy()
+    diff = float(np.linalg.norm(xm - x64n) / np.linalg.norm(x64n))
+    import oracle
+    rng = np.random.default_rng(1)
+    sites = [tuple(int(rng.integers(0, L)) for L in dims) for _ in range(8)]
+    Uh = Ut.cpu().numpy()
+    lhs = oracle.normal_op_sites(Uh, xm, MASS, sites)
+    rhs = oracle.wilson_D_sites(Uh, b, MASS, sites, dagger=True)
+    rms_b = float(np.sqrt(np.mean(np.abs(rhs) ** 2)))
+    sampled = float(np.abs(lhs - rhs).max() / rms_b)
+    del Uh
+
+    # Dslash roofline: D^+ in the inner storage precision, HIP events on one stream
+    reps = args.dslash_reps
+    stream = torch.cuda.Stream(dev)
+    dsl = {}
+    with torch.cuda.stream(stream):
+        for prec in [best, "f64"]:
+            Up = wd.pack_gauge(Ut, prec)
+            pin = wd.pack_spinor(bt, prec)
+            pout = wd.empty_packed_spinor(dims, prec, dev)
+            for _ in range(10):
+                wd.wilson_apply_packed(Up, pin, pout, dims, MASS, prec, True)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                wd.wilson_apply_packed(Up, pin, pout, dims, MASS, prec, True)
+            e1.record(stream)
+            e1.synchronize()
+            avg = e0.elapsed_time(e1) / 1e3 / reps
+            gbs = BYTES_PER_SITE[prec] * V / avg / 1e9
+            dsl[prec] = {"avg_us": avg * 1e6, "GB_per_s": gbs, "frac_hbm": gbs / HBM_PEAK_GBS,
+                         "sites_per_s": V / avg, "TFLOP_per_s": FLOPS_PER_SITE * V / avg / 1e12,
+                         "bytes_per_launch": BYTES_PER_SITE[prec] * V}
+            del Up, pin, pout
+    torch.cuda.synchronize()
+    log(f"dslash: {dsl}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, 1 core)")
+        cpu = run_cpu_baseline(dims, fp64["iterations"])
+
+    kern = dsl[best]
+    out = {
+        "metric": METRIC,
+        "value": per,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": per * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "storage": best,
+        "data": "synthetic",
+        "config": {"workload": "mixed-precision reliable-update CG on D^+D x = D^+b to true rel. residual 1e-10, "
+                               "Wilson-Dirac 32^3x64 periodic, m=0.02, links exp(i 0.3 H), Gaussian source",
+                   "lattice_xyzt": list(dims), "mass": MASS, "tol": TOL, "inner_storage": best,
+                   "reliable_interval": 50},
+        "mixed_cg": {"seconds": per, "iterations": infos[-1]["iterations"],
+                     "reliable_updates": infos[-1]["reliable_updates"], "true_rel_res": infos[-1]["true_rel_res"],
+                     "rel_diff_vs_fp64_solution": diff, "sampled_oracle_residual": sampled},
+        "fp64_cg": fp64,
+        "speedup_mixed_vs_fp64": fp64["seconds"] / per,
+        "variants": variants,
+        "dslash": dsl,
+        "roofline": {"bound": "hbm", "kernel": f"k_wilson_packed<{best}, dagger>", "achieved": kern["GB_per_s"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kern["frac_hbm"], "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,190 @@
+/*
+ * wilson.h -- C ABI of the MI355X (gfx950) Wilson-Dirac conjugate-gradient library.
+ *
+ * What is computed. The Wilson-Dirac operator on a periodic 4D lattice with
+ * 3x3 complex (SU(3)) link matrices acting on 12-component complex spinors
+ * (paper Sec. 1 and the Fig. 1 caption name the operator and its data; the
+ * definition is the one of the lattice-QCD textbook the paper cites there),
+ * in mass form with lattice spacing 1:
+ *
+ *   (D psi)(x) = (m + 4) psi(x)
+ *              - 1/2 sum_{mu=0..3} [ (1 - g_mu) U_mu(x) psi(x + mu)
+ *                                  + (1 + g_mu) U_mu(x - mu)^+ psi(x - mu) ]
+ *
+ * (equivalently (1 / 2 kappa)(1 - kappa H) with kappa = 1 / (2 m + 8)),
+ * g_mu the Euclidean chiral gamma matrices, mu = 0, 1, 2, 3 = x, y, z, t.
+ * D^+ is the same stencil with g_mu -> -g_mu. The solver is the
+ * conjugate-gradient method (Sec. 1, Sec. 3.1) on the normal equations
+ * D^+ D x = D^+ b, optionally in the two-precision form of Sec. 2 / Sec. 3.2
+ * (low-precision iterations corrected by occasional FP64 recomputation of
+ * the residual).
+ *
+ * Layouts at the boundary (row-major, x fastest):
+ *   lattice dims   L[0] = Lx, L[1] = Ly, L[2] = Lz, L[3] = Lt, each >= 2
+ *   gauge field U  complex128 (4, Lt, Lz, Ly, Lx, 3, 3); U[mu][site] is the
+ *                  colour matrix on the link site -> site + mu, row-major
+ *   spinor psi     (Lt, Lz, Ly, Lx, 4, 3) complex128 (or complex64 where an
+ *                  io_dtype says so): spin index then colour index
+ *   force F        same shape and type as U
+ *
+ * Pointers: every field pointer is DEVICE memory owned by the caller (for
+ * example a PyTorch tensor's data_ptr()); the library keeps no pointer after
+ * a call returns and never frees caller memory. `stream` is a hipStream_t
+ * (NULL = the default stream). Input and output fields must not overlap.
+ *
+ * Errors: every int-returning call returns WD_OK (0), WD_NOT_CONVERGED (1)
+ * or a negative WD_ERR_* code; wd_last_error() returns a message for the
+ * calling thread's last non-zero return. Argument errors are detected before
+ * any device work is issued. Nothing aborts or throws across the ABI.
+ */
+#ifndef WILSON_MI355X_H
+#define WILSON_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int32_t L[4]; /* Lx, Ly, Lz, Lt; each >= 2; Lx*Ly*Lz*Lt <= 2^28 */
+} wd_lattice;
+
+/* storage / arithmetic precision of the solver's inner iterations */
+enum { WD_F64 = 0, WD_F32 = 1, WD_BF16 = 2, WD_F16 = 3 };
+/* which system cg_solve solves */
+enum { WD_RHS_SOURCE = 0, /* D^+ D x = D^+ b  (x = D^-1 b) */
+       WD_RHS_NORMAL = 1  /* D^+ D x = b                   */ };
+/* element type of b and x at the boundary */
+enum { WD_C128 = 0, WD_C64 = 1 };
+
+enum {
+  WD_OK = 0,
+  WD_NOT_CONVERGED = 1,   /* max_iter reached; x holds the last iterate */
+  WD_ERR_INVALID = -1,    /* bad argument; nothing was launched */
+  WD_ERR_HIP = -2,        /* a HIP runtime call failed */
+  WD_ERR_BREAKDOWN = -3,  /* <p, D^+ D p> <= 0 */
+  WD_ERR_NAN = -4,        /* NaN or Inf in a reduction (for example a NaN in b) */
+  WD_ERR_WORKSPACE = -5   /* workspace NULL or smaller than wd_workspace_bytes() */
+};
+
+typedef struct {
+  double tol;                /* stop when ||b' - D^+ D x|| / ||b'|| <= tol (b' = D^+ b or b) */
+  int32_t max_iter;          /* CG iterations (inner iterations for mixed precision) */
+  int32_t inner_prec;        /* WD_F64: plain FP64 CG. WD_F32 / WD_BF16 / WD_F16: FP32
+                                arithmetic on that storage, FP64 reliable updates */
+  int32_t reliable_interval; /* mixed only: FP64 residual recomputation every this many
+                                iterations (0 -> 50) */
+  int32_t rhs_mode;          /* WD_RHS_SOURCE or WD_RHS_NORMAL */
+  int32_t io_dtype;          /* WD_C128 or WD_C64: element type of b and x */
+  int32_t zero_guess;        /* nonzero: start from x = 0 and ignore x's input contents */
+  double* history;           /* HOST array, may be NULL: iterated relative residual per iteration */
+  int32_t history_len;       /* capacity of history (entries beyond are dropped) */
+  int32_t pad;
+} wd_cg_params;
+
+typedef struct {
+  int32_t iterations;        /* iterations performed (inner iterations for mixed) */
+  int32_t reliable_updates;  /* FP64 residual recomputations (mixed) */
+  int32_t status;            /* same value as the call's return code */
+  int32_t pad;
+  double true_rel_res;       /* ||b' - D^+ D x|| / ||b'|| recomputed in FP64 at the end */
+  double iter_rel_res;       /* the recurrence's own residual at the end */
+  double seconds;            /* host wall time of the call */
+} wd_cg_result;
+
+/* Thread-local text of the last non-zero return on the calling thread. */
+const char* wd_last_error(void);
+
+/* Number of HIP devices visible, or a negative WD_ERR_HIP. */
+int wd_device_count(void);
+
+/*
+ * out = D psi. U, psi, out: device, canonical complex128 layouts above.
+ * Asynchronous on `stream`; no host synchronisation, no workspace.
+ */
+int wilson_apply(const wd_lattice* lat, double mass, const void* U, const void* psi, void* out, void* stream);
+
+/* out = D^+ psi (the same stencil with g_mu -> -g_mu). As wilson_apply. */
+int wilson_apply_dagger(const wd_lattice* lat, double mass, const void* U, const void* psi, void* out,
+                        void* stream);
+
+/*
+ * Device workspace needed by cg_solve (nrhs = 1) or cg_solve_batched
+ * (nrhs = number of right-hand sides) for these parameters, in bytes.
+ * Returns 0 on an invalid argument (see wd_last_error()).
+ */
+size_t wd_workspace_bytes(const wd_lattice* lat, const wd_cg_params* params, int32_t nrhs);
+
+/*
+ * Solve D^+ D x = D^+ b (rhs_mode WD_RHS_SOURCE) or D^+ D x = b
+ * (WD_RHS_NORMAL) by conjugate gradient.
+ *   U          device, canonical complex128 gauge field
+ *   b          device, canonical spinor of element type params->io_dtype
+ *   x          device, same type: initial guess on entry (unless
+ *              params->zero_guess), solution on return
+ *   workspace  device, at least wd_workspace_bytes(lat, params, 1) bytes,
+ *              owned by the caller, contents need not be initialised
+ *   result     host, filled on return (may be NULL)
+ * Runs on `stream` and BLOCKS until the solve ends (the host polls the
+ * device-side residual to stop). Returns WD_OK, WD_NOT_CONVERGED (x holds the
+ * last iterate, usable as a restart guess) or a WD_ERR_* code.
+ */
+int cg_solve(const wd_lattice* lat, double mass, const void* U, const void* b, void* x,
+             const wd_cg_params* params, wd_cg_result* result, void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Solve nrhs systems sharing one gauge field in ONE persistent cooperative
+ * launch. B, X: device, (nrhs, Lt, Lz, Ly, Lx, 4, 3) of element type
+ * params->io_dtype. Inner iterations run in FP32 on FP32 fields with every
+ * link load reused across all right-hand sides; each system carries its own
+ * alpha, beta and convergence mask; FP64 reliable updates every
+ * params->reliable_interval iterations recompute each residual from an FP64
+ * solution. results: host array of nrhs entries (may be NULL).
+ * 1 <= nrhs <= 16. Blocks until all systems end. Returns WD_OK if every
+ * system converged, WD_NOT_CONVERGED if any did not, or a WD_ERR_* code.
+ */
+int cg_solve_batched(const wd_lattice* lat, double mass, const void* U, int32_t nrhs, const void* B, void* X,
+                     const wd_cg_params* params, wd_cg_result* results, void* workspace, size_t ws_bytes,
+                     void* stream);
+
+/*
+ * Gauge-link gradient kernel (the derivative of 1/2 Re<a, H b> with respect to
+ * the links, in the convention grad = d/dRe U + i d/dIm U):
+ *   G(a, b)_mu(x) = 1/2 sum_spin [ ((1 - g_mu) a(x)) (x) b(x + mu)^*
+ *                                + b(x) (x) ((1 + g_mu) a(x + mu))^* ]
+ * with (u (x) v^*)_ij = u_i conj(v_j). F = coeff * G(a, b), or F += coeff * G(a, b)
+ * when accumulate is nonzero. a, b: device canonical complex128 spinors;
+ * F: device canonical complex128 gauge-shaped field. Asynchronous on `stream`.
+ * For chi = (D^+D)^-1 phi and an upstream gradient g, lambda = (D^+D)^-1 g:
+ *   dL/dU = G(D chi, lambda) + G(D lambda, chi).
+ */
+int wilson_force(const wd_lattice* lat, const void* a, const void* b, double coeff, int32_t accumulate, void* F,
+                 void* stream);
+
+/* ---- packed fields: the solver's internal site-blocked layout, for callers that
+ *      apply D repeatedly without repacking (and for timing the hot kernel). ---- */
+
+/* Bytes of a packed gauge field / spinor field in precision `prec` (0 on bad args). */
+size_t wd_gauge_bytes(const wd_lattice* lat, int32_t prec);
+size_t wd_spinor_bytes(const wd_lattice* lat, int32_t prec);
+
+/* Pack canonical complex128 U into `out` (device, wd_gauge_bytes bytes). Asynchronous. */
+int wd_pack_gauge(const wd_lattice* lat, const void* U, int32_t prec, void* out, void* stream);
+/* Canonical spinor (element type io_dtype) <-> packed spinor of precision prec. Asynchronous. */
+int wd_pack_spinor(const wd_lattice* lat, const void* in, int32_t io_dtype, int32_t prec, void* out, void* stream);
+int wd_unpack_spinor(const wd_lattice* lat, const void* in, int32_t prec, void* out, int32_t io_dtype,
+                     void* stream);
+
+/* out = D in (dagger = 0) or D^+ in on packed fields of precision prec (FP32
+ * arithmetic for WD_F32/WD_BF16/WD_F16, FP64 for WD_F64). The kernel of the
+ * solver's inner iterations. Asynchronous. */
+int wilson_apply_packed(const wd_lattice* lat, double mass, int32_t prec, const void* U_packed,
+                        const void* in_packed, void* out_packed, int32_t dagger, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WILSON_MI355X_H */

@@ -1,0 +1,557 @@
+// C ABI of the Wilson-Dirac library: argument validation, workspace layout,
+// and the host side of the conjugate-gradient drivers.
+//
+// The paper's host part owns the CG vectors and evaluates the stopping test
+// on the host, invoking the accelerator once per operator application
+// (Sec. 3.1, Sec. 3.1.1). Here every vector and every CG scalar stays in HBM:
+// the reductions finish on the device (last-workgroup-done), alpha and beta
+// never leave it, and the host only enqueues chunks of iterations and polls a
+// copy of the device state between chunks. A device-side status flag turns
+// the kernels of iterations enqueued past convergence into no-ops.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "../../include/wilson.h"
+#include "wd_internal.hpp"
+
+using namespace wd;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(call)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess) return fail(WD_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_));     \
+  } while (0)
+
+int check_lattice(const wd_lattice* lat) {
+  if (!lat) return fail(WD_ERR_INVALID, "lattice is NULL");
+  long long v = 1;
+  for (int i = 0; i < 4; ++i) {
+    if (lat->L[i] < 2) return fail(WD_ERR_INVALID, "lattice extent L[%d] = %d (must be >= 2)", i, lat->L[i]);
+    if (lat->L[i] > (1 << 20)) return fail(WD_ERR_INVALID, "lattice extent L[%d] = %d too large", i, lat->L[i]);
+    v *= lat->L[i];
+  }
+  if (v > (1ll << 28)) return fail(WD_ERR_INVALID, "lattice volume %lld exceeds 2^28 sites", v);
+  return WD_OK;
+}
+
+bool valid_prec(int p) { return p == WD_F64 || p == WD_F32 || p == WD_BF16 || p == WD_F16; }
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+size_t align_up(size_t n) { return (n + 255) & ~size_t(255); }
+
+// Carves a caller-owned workspace into 256-byte aligned pieces.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  void* take(size_t n) {
+    void* p = base ? base + off : nullptr;
+    off += align_up(n);
+    return p;
+  }
+};
+
+SpinorBuf take_spinor(Carver& c, int prec, const Geom& g) {
+  SpinorBuf b;
+  b.prec = prec;
+  b.data = c.take(spinor_bytes(prec, g.Vpad));
+  b.scale = prec == P_F16 ? static_cast<float*>(c.take(spinor_scale_bytes(prec, g.Vpad))) : nullptr;
+  return b;
+}
+
+// Layout of the single-RHS solver workspace. With base == nullptr it only
+// measures.
+struct CgWorkspace {
+  SolverState* st;
+  double* partials;
+  double* hist;
+  void* U64;
+  void* Ulow;
+  SpinorBuf b64, x64, r64, p64, t64;   // plain FP64 CG (r64/p64 unused by mixed)
+  SpinorBuf ph, rh, th, xh;             // mixed: low-precision p, r, t; FP32 x-hat
+  size_t bytes;
+};
+
+CgWorkspace layout_cg(void* base, const Geom& g, int inner, int hist_len) {
+  Carver c(base);
+  CgWorkspace w{};
+  w.st = static_cast<SolverState*>(c.take(sizeof(SolverState)));
+  w.partials = static_cast<double*>(c.take(sizeof(double) * (size_t)g.nblocks));
+  w.hist = static_cast<double*>(c.take(sizeof(double) * (size_t)(hist_len > 0 ? hist_len : 1)));
+  w.U64 = c.take(gauge_bytes(P_F64, g.Vpad));
+  w.b64 = take_spinor(c, P_F64, g);
+  w.x64 = take_spinor(c, P_F64, g);
+  w.t64 = take_spinor(c, P_F64, g);
+  if (inner == WD_F64) {
+    w.r64 = take_spinor(c, P_F64, g);
+    w.p64 = take_spinor(c, P_F64, g);
+  } else {
+    w.Ulow = c.take(gauge_bytes(inner, g.Vpad));
+    w.ph = take_spinor(c, inner, g);
+    w.rh = take_spinor(c, inner, g);
+    w.th = take_spinor(c, inner, g);
+    w.xh = take_spinor(c, P_F32, g);
+  }
+  w.bytes = c.off;
+  return w;
+}
+
+// Host mirrors of the device state, pinned, one pair per device.
+struct HostMirror {
+  SolverState* buf[2] = {nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+};
+std::mutex g_mirror_mu;
+HostMirror g_mirror[64];
+
+int get_mirror(HostMirror** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(WD_ERR_HIP, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_mirror_mu);
+  HostMirror& m = g_mirror[dev];
+  if (!m.buf[0]) {
+    for (int i = 0; i < 2; ++i) {
+      HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&m.buf[i]), sizeof(SolverState), hipHostMallocDefault));
+      HIP_TRY(hipEventCreateWithFlags(&m.ev[i], hipEventDisableTiming));
+    }
+  }
+  *out = &m;
+  return WD_OK;
+}
+
+int fill_result(wd_cg_result* res, const SolverState& st, int code, double secs, double iter_rel) {
+  if (!res) return code;
+  res->iterations = st.iter;
+  res->reliable_updates = st.rel_updates;
+  res->status = code;
+  res->pad = 0;
+  const double bn = st.bnorm2 > 0 ? st.bnorm2 : 1.0;
+  res->true_rel_res = std::sqrt(st.rho_true / bn);
+  res->iter_rel_res = iter_rel;
+  res->seconds = secs;
+  return code;
+}
+
+int status_to_code(int status) {
+  if (status == 1) return WD_OK;
+  if (status == -3) return fail(WD_ERR_BREAKDOWN, "CG breakdown: <p, D^+D p> <= 0");
+  if (status == -4) return fail(WD_ERR_NAN, "NaN or Inf encountered in a CG reduction");
+  return WD_OK;
+}
+
+int validate_params(const wd_cg_params* p) {
+  if (!p) return fail(WD_ERR_INVALID, "params is NULL");
+  if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return fail(WD_ERR_INVALID, "tol = %g must be positive", p->tol);
+  if (p->max_iter < 1) return fail(WD_ERR_INVALID, "max_iter = %d must be >= 1", p->max_iter);
+  if (!valid_prec(p->inner_prec)) return fail(WD_ERR_INVALID, "inner_prec = %d unknown", p->inner_prec);
+  if (p->reliable_interval < 0) return fail(WD_ERR_INVALID, "reliable_interval = %d", p->reliable_interval);
+  if (p->rhs_mode != WD_RHS_SOURCE && p->rhs_mode != WD_RHS_NORMAL)
+    return fail(WD_ERR_INVALID, "rhs_mode = %d unknown", p->rhs_mode);
+  if (p->io_dtype != WD_C128 && p->io_dtype != WD_C64) return fail(WD_ERR_INVALID, "io_dtype = %d unknown", p->io_dtype);
+  if (p->history_len < 0) return fail(WD_ERR_INVALID, "history_len = %d", p->history_len);
+  if (p->history_len > 0 && !p->history) return fail(WD_ERR_INVALID, "history is NULL but history_len > 0");
+  return WD_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+
+extern "C" {
+
+const char* wd_last_error(void) { return g_err.c_str(); }
+
+int wd_device_count(void) {
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess) return fail(WD_ERR_HIP, "hipGetDeviceCount: %s", hipGetErrorString(e));
+  return n;
+}
+
+static int apply_common(const wd_lattice* lat, double mass, const void* U, const void* psi, void* out, void* stream,
+                        int dagger) {
+  int rc = check_lattice(lat);
+  if (rc) return rc;
+  if (!U || !psi || !out) return fail(WD_ERR_INVALID, "NULL field pointer");
+  if (psi == out) return fail(WD_ERR_INVALID, "in and out must not alias");
+  if (!std::isfinite(mass)) return fail(WD_ERR_INVALID, "mass is not finite");
+  const Geom g = make_geom(lat->L);
+  launch_wilson_canonical(g, U, psi, out, mass, dagger, as_stream(stream));
+  HIP_TRY(hipGetLastError());
+  return WD_OK;
+}
+
+int wilson_apply(const wd_lattice* lat, double mass, const void* U, const void* psi, void* out, void* stream) {
+  return apply_common(lat, mass, U, psi, out, stream, 0);
+}
+
+int wilson_apply_dagger(const wd_lattice* lat, double mass, const void* U, const void* psi, void* out,
+                        void* stream) {
+  return apply_common(lat, mass, U, psi, out, stream, 1);
+}
+
+size_t wd_gauge_bytes(const wd_lattice* lat, int32_t prec) {
+  if (check_lattice(lat)) return 0;
+  if (!valid_prec(prec)) { fail(WD_ERR_INVALID, "prec = %d unknown", prec); return 0; }
+  return gauge_bytes(prec, make_geom(lat->L).Vpad);
+}
+
+size_t wd_spinor_bytes(const wd_lattice* lat, int32_t prec) {
+  if (check_lattice(lat)) return 0;
+  if (!valid_prec(prec)) { fail(WD_ERR_INVALID, "prec = %d unknown", prec); return 0; }
+  const Geom g = make_geom(lat->L);
+  return spinor_bytes(prec, g.Vpad) + spinor_scale_bytes(prec, g.Vpad);
+}
+
+static SpinorBuf packed_view(const Geom& g, int prec, const void* p) {
+  SpinorBuf b;
+  b.prec = prec;
+  b.data = const_cast<void*>(p);
+  b.scale = prec == P_F16 ? reinterpret_cast<float*>(static_cast<char*>(b.data) + spinor_bytes(prec, g.Vpad))
+                          : nullptr;
+  return b;
+}
+
+int wd_pack_gauge(const wd_lattice* lat, const void* U, int32_t prec, void* out, void* stream) {
+  int rc = check_lattice(lat);
+  if (rc) return rc;
+  if (!valid_prec(prec)) return fail(WD_ERR_INVALID, "prec = %d unknown", prec);
+  if (!U || !out) return fail(WD_ERR_INVALID, "NULL field pointer");
+  launch_pack_gauge(make_geom(lat->L), U, prec, out, as_stream(stream));
+  HIP_TRY(hipGetLastError());
+  return WD_OK;
+}
+
+int wd_pack_spinor(const wd_lattice* lat, const void* in, int32_t io_dtype, int32_t prec, void* out, void* stream) {
+  int rc = check_lattice(lat);
+  if (rc) return rc;
+  if (!valid_prec(prec)) return fail(WD_ERR_INVALID, "prec = %d unknown", prec);
+  if (io_dtype != WD_C128 && io_dtype != WD_C64) return fail(WD_ERR_INVALID, "io_dtype = %d unknown", io_dtype);
+  if (!in || !out) return fail(WD_ERR_INVALID, "NULL field pointer");
+  const Geom g = make_geom(lat->L);
+  launch_pack_spinor(g, in, io_dtype == WD_C64, packed_view(g, prec, out), as_stream(stream));
+  HIP_TRY(hipGetLastError());
+  return WD_OK;
+}
+
+int wd_unpack_spinor(const wd_lattice* lat, const void* in, int32_t prec, void* out, int32_t io_dtype,
+                     void* stream) {
+  int rc = check_lattice(lat);
+  if (rc) return rc;
+  if (!valid_prec(prec)) return fail(WD_ERR_INVALID, "prec = %d unknown", prec);
+  if (io_dtype != WD_C128 && io_dtype != WD_C64) return fail(WD_ERR_INVALID, "io_dtype = %d unknown", io_dtype);
+  if (!in || !out) return fail(WD_ERR_INVALID, "NULL field pointer");
+  const Geom g = make_geom(lat->L);
+  launch_unpack_spinor(g, packed_view(g, prec, in), out, io_dtype == WD_C64, as_stream(stream));
+  HIP_TRY(hipGetLastError());
+  return WD_OK;
+}
+
+int wilson_apply_packed(const wd_lattice* lat, double mass, int32_t prec, const void* U_packed,
+                        const void* in_packed, void* out_packed, int32_t dagger, void* stream) {
+  int rc = check_lattice(lat);
+  if (rc) return rc;
+  if (!valid_prec(prec)) return fail(WD_ERR_INVALID, "prec = %d unknown", prec);
+  if (!U_packed || !in_packed || !out_packed) return fail(WD_ERR_INVALID, "NULL field pointer");
+  if (in_packed == out_packed) return fail(WD_ERR_INVALID, "in and out must not alias");
+  const Geom g = make_geom(lat->L);
+  launch_wilson_packed(g, prec, U_packed, packed_view(g, prec, in_packed), packed_view(g, prec, out_packed), mass,
+                       dagger ? 1 : 0, G_ALWAYS, F_NONE, nullptr, nullptr, as_stream(stream));
+  HIP_TRY(hipGetLastError());
+  return WD_OK;
+}
+
+int wilson_force(const wd_lattice* lat, const void* a, const void* b, double coeff, int32_t accumulate, void* F,
+                 void* stream) {
+  int rc = check_lattice(lat);
+  if (rc) return rc;
+  if (!a || !b || !F) return fail(WD_ERR_INVALID, "NULL field pointer");
+  if (!std::isfinite(coeff)) return fail(WD_ERR_INVALID, "coeff is not finite");
+  launch_force(make_geom(lat->L), a, b, coeff, accumulate ? 1 : 0, F, as_stream(stream));
+  HIP_TRY(hipGetLastError());
+  return WD_OK;
+}
+
+size_t wd_workspace_bytes(const wd_lattice* lat, const wd_cg_params* params, int32_t nrhs) {
+  if (check_lattice(lat)) return 0;
+  if (validate_params(params)) return 0;
+  if (nrhs < 1) { fail(WD_ERR_INVALID, "nrhs = %d must be >= 1", nrhs); return 0; }
+  const Geom g = make_geom(lat->L);
+  if (nrhs == 1) return layout_cg(nullptr, g, params->inner_prec, params->history_len).bytes;
+  if (nrhs > 16) { fail(WD_ERR_INVALID, "nrhs = %d exceeds 16", nrhs); return 0; }
+  return batched_workspace_bytes(g, nrhs, params->history_len);
+}
+
+}  // extern "C"
+
+// ============================================================ CG drivers
+
+namespace {
+
+// Polls device state between chunks of enqueued iterations. Two chunks are
+// in flight: while the host waits for chunk k, chunk k + 1 is already queued.
+struct Poller {
+  HostMirror* m;
+  SolverState* dst;
+  hipStream_t s;
+  int slot = 0;
+  int pending = 0;
+  int post(SolverState* st) {
+    HIP_TRY(hipMemcpyAsync(m->buf[slot], st, sizeof(SolverState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(m->ev[slot], s));
+    slot ^= 1;
+    ++pending;
+    return WD_OK;
+  }
+  // Wait for the oldest posted copy.
+  int wait(SolverState* out) {
+    const int k = pending == 2 ? slot : slot ^ 1;
+    HIP_TRY(hipEventSynchronize(m->ev[k]));
+    *out = *m->buf[k];
+    --pending;
+    return WD_OK;
+  }
+  int drain(SolverState* out) {
+    while (pending > 0) {
+      int rc = wait(out);
+      if (rc) return rc;
+    }
+    return WD_OK;
+  }
+};
+
+// Iterations to enqueue next, from the observed convergence rate.
+int next_chunk(const SolverState& s, int enqueued, int max_iter) {
+  int left = max_iter - enqueued;
+  if (left <= 0) return 0;
+  int n = 16;
+  if (s.iter >= 4 && s.rho > 0 && s.bnorm2 > 0 && s.stop2 > 0) {
+    const double rate = std::log(s.rho / s.bnorm2) / s.iter;  // < 0 when converging
+    if (rate < 0) {
+      const double need = std::log(s.stop2 / s.bnorm2) - std::log(s.rho / s.bnorm2);
+      const int est = (int)std::ceil(need / rate);
+      n = std::max(2, std::min(32, est / 2 + 1));
+    }
+  }
+  return std::min(n, left);
+}
+
+int copy_history(const CgWorkspace& w, const wd_cg_params* p, hipStream_t s, int iters) {
+  if (!p->history || p->history_len <= 0) return WD_OK;
+  const int n = std::min(iters, p->history_len);
+  if (n > 0) HIP_TRY(hipMemcpyAsync(p->history, w.hist, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int i = n; i < p->history_len; ++i) p->history[i] = 0.0;
+  return WD_OK;
+}
+
+// Shared set-up: pack U and b, form b', zero or pack x, and the initial
+// residual r = b' - D^+ D x written to `rout` in its precision.
+int cg_setup(const Geom& g, double mass, const void* U, const void* b, void* x, const wd_cg_params* p,
+             const CgWorkspace& w, int interval, double delta, SpinorBuf rout, hipStream_t s) {
+  launch_init_state(w.st, p->tol, interval, delta, w.hist, p->history_len, s);
+  launch_pack_gauge(g, U, P_F64, w.U64, s);
+  const int c64 = p->io_dtype == WD_C64;
+  if (p->rhs_mode == WD_RHS_SOURCE) {
+    launch_pack_spinor(g, b, c64, w.t64, s);
+    launch_wilson_packed(g, P_F64, w.U64, w.t64, w.b64, mass, 1, G_ALWAYS, F_NONE, w.st, w.partials, s);
+  } else {
+    launch_pack_spinor(g, b, c64, w.b64, s);
+  }
+  launch_norm2(g, w.b64, G_ALWAYS, F_BNORM, w.st, w.partials, s);
+  if (p->zero_guess) launch_zero(g, w.x64, G_ALWAYS, w.st, s);
+  else launch_pack_spinor(g, x, c64, w.x64, s);
+  launch_wilson_packed(g, P_F64, w.U64, w.x64, w.t64, mass, 0, G_ALWAYS, F_NONE, w.st, w.partials, s);
+  launch_residual(g, w.U64, w.t64, w.b64, rout, mass, G_ALWAYS, F_RHO_INIT, w.st, w.partials, s);
+  HIP_TRY(hipGetLastError());
+  return WD_OK;
+}
+
+int cg_plain(const Geom& g, double mass, const void* U, const void* b, void* x, const wd_cg_params* p,
+             wd_cg_result* res, void* ws, hipStream_t s, std::chrono::steady_clock::time_point t0) {
+  const CgWorkspace w = layout_cg(ws, g, WD_F64, p->history_len);
+  int rc = cg_setup(g, mass, U, b, x, p, w, 0, 0.0, w.r64, s);
+  if (rc) return rc;
+  launch_convert(g, w.r64, w.p64, G_ALWAYS, w.st, s);
+
+  HostMirror* m;
+  if ((rc = get_mirror(&m))) return rc;
+  Poller poll{m, nullptr, s};
+  SolverState st{};
+  st.stop2 = 1;
+  int enqueued = 0;
+  int restarts = 0;
+  for (;;) {
+    // keep two chunks in flight
+    while (poll.pending < 2) {
+      const int n = next_chunk(st, enqueued, p->max_iter);
+      if (n <= 0) break;
+      for (int k = 0; k < n; ++k) {
+        launch_wilson_packed(g, P_F64, w.U64, w.p64, w.t64, mass, 0, G_ITER, F_ALPHA, w.st, w.partials, s);
+        launch_cg_update(g, P_F64, w.U64, w.t64, w.r64, w.p64, w.x64, mass, w.st, w.partials, s);
+        launch_p_update(g, w.r64, w.p64, w.st, s);
+      }
+      enqueued += n;
+      HIP_TRY(hipGetLastError());
+      if ((rc = poll.post(w.st))) return rc;
+    }
+    if (poll.pending == 0) break;
+    if ((rc = poll.wait(&st))) return rc;
+    if (st.status != 0) {
+      if ((rc = poll.drain(&st))) return rc;
+      if (st.status != 1) break;
+      // verify with the FP64 residual recomputed from x
+      launch_wilson_packed(g, P_F64, w.U64, w.x64, w.t64, mass, 0, G_FINAL, F_NONE, w.st, w.partials, s);
+      launch_residual(g, w.U64, w.t64, w.b64, w.r64, mass, G_FINAL, F_TRUE, w.st, w.partials, s);
+      if ((rc = poll.post(w.st))) return rc;
+      if ((rc = poll.drain(&st))) return rc;
+      if (st.rho_true <= st.stop2 || enqueued >= p->max_iter || restarts >= 5) break;
+      // the recurrence drifted from the true residual: restart from it
+      ++restarts;
+      launch_restart(w.st, s);
+      launch_convert(g, w.r64, w.p64, G_ALWAYS, w.st, s);
+      HIP_TRY(hipGetLastError());
+      continue;
+    }
+  }
+  if ((rc = poll.drain(&st))) return rc;
+  double iter_rel = std::sqrt(st.rho / (st.bnorm2 > 0 ? st.bnorm2 : 1.0));
+  if (st.status != 1 || st.rho_true > st.stop2) {
+    if (st.status == 0 || st.status == 1) {
+      // not converged within max_iter: report the true residual of the last iterate
+      launch_wilson_packed(g, P_F64, w.U64, w.x64, w.t64, mass, 0, G_FINAL, F_NONE, w.st, w.partials, s);
+      launch_residual(g, w.U64, w.t64, w.b64, w.r64, mass, G_FINAL, F_TRUE, w.st, w.partials, s);
+      if ((rc = poll.post(w.st))) return rc;
+      if ((rc = poll.drain(&st))) return rc;
+    }
+  }
+  launch_unpack_spinor(g, w.x64, x, p->io_dtype == WD_C64, s);
+  HIP_TRY(hipGetLastError());
+  if ((rc = copy_history(w, p, s, st.iter))) return rc;
+  HIP_TRY(hipStreamSynchronize(s));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int code;
+  if (st.status < 0) code = status_to_code(st.status);
+  else if (st.rho_true <= st.stop2) code = WD_OK;
+  else code = fail(WD_NOT_CONVERGED, "not converged in %d iterations (true rel. residual %.3e)", st.iter,
+                   std::sqrt(st.rho_true / (st.bnorm2 > 0 ? st.bnorm2 : 1.0)));
+  return fill_result(res, st, code, secs, iter_rel);
+}
+
+// Reliable-update mixed precision: inner CG in FP32 arithmetic on
+// low-precision fields; the solution accumulates in FP32 between updates and
+// is flushed into FP64 x, where the residual is recomputed exactly.
+int cg_mixed(const Geom& g, double mass, const void* U, const void* b, void* x, const wd_cg_params* p,
+             wd_cg_result* res, void* ws, hipStream_t s, std::chrono::steady_clock::time_point t0) {
+  const int P = p->inner_prec;
+  const int interval = p->reliable_interval > 0 ? p->reliable_interval : 50;
+  const CgWorkspace w = layout_cg(ws, g, P, p->history_len);
+  // Besides every `interval` iterations, recompute the residual whenever the
+  // iterated residual has fallen by `delta` since the last update, so that
+  // the low-precision drift (~ unit roundoff x the residual at the last
+  // update) stays well below the residual being iterated.
+  const double delta = (P == WD_BF16) ? 0.1 : (P == WD_F16) ? 1e-2 : 1e-4;
+  int rc = cg_setup(g, mass, U, b, x, p, w, interval, delta, w.rh, s);
+  if (rc) return rc;
+  launch_pack_gauge(g, U, P, w.Ulow, s);
+  launch_zero(g, w.xh, G_ALWAYS, w.st, s);
+  launch_convert(g, w.rh, w.ph, G_ALWAYS, w.st, s);
+  HIP_TRY(hipGetLastError());
+
+  HostMirror* m;
+  if ((rc = get_mirror(&m))) return rc;
+  Poller poll{m, nullptr, s};
+  SolverState st{};
+  st.stop2 = 1;
+  int enqueued = 0;
+  const int slot_every = 5;   // a reliable-update slot after every 5th enqueued iteration
+  for (;;) {
+    while (poll.pending < 2) {
+      int n = next_chunk(st, enqueued, p->max_iter);
+      if (n <= 0) break;
+      for (int k = 0; k < n; ++k) {
+        launch_wilson_packed(g, P, w.Ulow, w.ph, w.th, mass, 0, G_ITER, F_ALPHA, w.st, w.partials, s);
+        launch_cg_update(g, P, w.Ulow, w.th, w.rh, w.ph, w.xh, mass, w.st, w.partials, s);
+        if ((enqueued + k + 1) % slot_every == 0) {
+          launch_accumulate(g, w.x64, w.xh, G_RELIABLE, w.st, s);
+          launch_wilson_packed(g, P_F64, w.U64, w.x64, w.t64, mass, 0, G_RELIABLE, F_NONE, w.st, w.partials, s);
+          launch_residual(g, w.U64, w.t64, w.b64, w.rh, mass, G_RELIABLE, F_RELIABLE, w.st, w.partials, s);
+        }
+        launch_p_update(g, w.rh, w.ph, w.st, s);
+      }
+      enqueued += n;
+      HIP_TRY(hipGetLastError());
+      if ((rc = poll.post(w.st))) return rc;
+    }
+    if (poll.pending == 0) break;
+    if ((rc = poll.wait(&st))) return rc;
+    if (st.status != 0) break;
+    if (st.inner_done && enqueued >= p->max_iter) break;
+  }
+  if ((rc = poll.drain(&st))) return rc;
+  const double iter_rel = std::sqrt(st.rho / (st.bnorm2 > 0 ? st.bnorm2 : 1.0));
+  if (st.status != 1) {
+    // max_iter reached (or an error): flush x-hat and measure the true residual
+    launch_accumulate(g, w.x64, w.xh, G_FINAL, w.st, s);
+    launch_wilson_packed(g, P_F64, w.U64, w.x64, w.t64, mass, 0, G_FINAL, F_NONE, w.st, w.partials, s);
+    launch_residual(g, w.U64, w.t64, w.b64, w.rh, mass, G_FINAL, F_TRUE, w.st, w.partials, s);
+    if ((rc = poll.post(w.st))) return rc;
+    if ((rc = poll.drain(&st))) return rc;
+  }
+  launch_unpack_spinor(g, w.x64, x, p->io_dtype == WD_C64, s);
+  HIP_TRY(hipGetLastError());
+  if ((rc = copy_history(w, p, s, st.iter))) return rc;
+  HIP_TRY(hipStreamSynchronize(s));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int code;
+  if (st.status < 0) code = status_to_code(st.status);
+  else if (st.rho_true <= st.stop2) code = WD_OK;
+  else code = fail(WD_NOT_CONVERGED, "not converged in %d iterations (true rel. residual %.3e)", st.iter,
+                   std::sqrt(st.rho_true / (st.bnorm2 > 0 ? st.bnorm2 : 1.0)));
+  return fill_result(res, st, code, secs, iter_rel);
+}
+
+}  // namespace
+
+extern "C" int cg_solve(const wd_lattice* lat, double mass, const void* U, const void* b, void* x,
+                        const wd_cg_params* params, wd_cg_result* result, void* workspace, size_t ws_bytes,
+                        void* stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (result) std::memset(result, 0, sizeof(*result));
+  int rc = check_lattice(lat);
+  if (rc) return rc;
+  if ((rc = validate_params(params))) return rc;
+  if (!U || !b || !x) return fail(WD_ERR_INVALID, "NULL field pointer");
+  if (b == x) return fail(WD_ERR_INVALID, "b and x must not alias");
+  if (!std::isfinite(mass)) return fail(WD_ERR_INVALID, "mass is not finite");
+  const Geom g = make_geom(lat->L);
+  const size_t need = layout_cg(nullptr, g, params->inner_prec, params->history_len).bytes;
+  if (!workspace || ws_bytes < need)
+    return fail(WD_ERR_WORKSPACE, "workspace of %zu bytes given, %zu needed", workspace ? ws_bytes : 0, need);
+  const hipStream_t s = as_stream(stream);
+  if (params->inner_prec == WD_F64) return cg_plain(g, mass, U, b, x, params, result, workspace, s, t0);
+  return cg_mixed(g, mass, U, b, x, params, result, workspace, s, t0);
+}

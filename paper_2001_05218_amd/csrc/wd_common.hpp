@@ -1,0 +1,373 @@
+// Common device types for the Wilson-Dirac library (gfx950 / CDNA4).
+//
+// Storage precisions, lattice geometry with division-free neighbour lookup,
+// and the packed (site-blocked, structure-of-arrays) field layouts used on the
+// solver's hot loop.
+//
+// Packed layouts. Sites are grouped in blocks of 64 (one wavefront). Within a
+// block every per-site record is split into fixed-width words and stored
+// word-major, so that lane l of a wavefront reading word w of its own site
+// touches address (block, w, l): each load instruction is one contiguous,
+// fully coalesced 64 x word-width span.
+//   spinor FP64 : 12 words x 16 B (one complex<double> per word)
+//   spinor FP32 :  6 words x 16 B (two complex<float>)
+//   spinor BF16 :  3 words x 16 B (four complex<bf16>)
+//   spinor FP16 :  3 words x 16 B (four complex<fp16>) + one FP32 scale per site
+//   links        : per site 4 directions x 9 words, one complex entry per
+//                  word (16 B FP64, 8 B FP32, 4 B BF16/FP16), row-major colour
+// The padded volume Vpad rounds V up to a multiple of 256 sites (one
+// workgroup); padding sites are never read as neighbours and never written.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wd {
+
+enum Prec : int { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_F16 = 3 };
+
+constexpr int kBlock = 256;      // threads per workgroup (4 wavefronts)
+constexpr int kSiteBlock = 64;   // sites per layout block (one wavefront)
+
+// ---------------------------------------------------------------- geometry
+
+// Division by a runtime constant d via one 64-bit multiply: exact for
+// numerators below 2^31 (q = floor(n * m / 2^k), m = ceil(2^k / d),
+// k = 31 + ceil(log2 d); then n * (m d - 2^k) < 2^k).
+struct FastDiv {
+  uint64_t m;
+  uint32_t k;
+  uint32_t d;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+  uint32_t l = 0;
+  while ((1ull << l) < d) ++l;
+  FastDiv f;
+  f.k = 31 + l;
+  f.m = (((1ull << f.k) + d - 1) / d);
+  f.d = d;
+  return f;
+}
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
+  return (uint32_t)(((uint64_t)n * f.m) >> f.k);
+}
+
+struct Geom {
+  int L[4];        // Lx, Ly, Lz, Lt
+  int V;           // sites
+  int Vpad;        // V rounded up to kBlock
+  int nblocks;     // Vpad / kBlock
+  int stride[4];   // 1, Lx, Lx*Ly, Lx*Ly*Lz
+  FastDiv dx, dy, dz;
+};
+
+inline Geom make_geom(const int L[4]) {
+  Geom g;
+  for (int i = 0; i < 4; ++i) g.L[i] = L[i];
+  g.V = L[0] * L[1] * L[2] * L[3];
+  g.Vpad = (g.V + kBlock - 1) / kBlock * kBlock;
+  g.nblocks = g.Vpad / kBlock;
+  g.stride[0] = 1;
+  g.stride[1] = L[0];
+  g.stride[2] = L[0] * L[1];
+  g.stride[3] = L[0] * L[1] * L[2];
+  g.dx = make_fastdiv(L[0]);
+  g.dy = make_fastdiv(L[1]);
+  g.dz = make_fastdiv(L[2]);
+  return g;
+}
+
+// Forward and backward neighbour indices of site s in all four directions.
+struct Nbrs {
+  int fwd[4];
+  int bwd[4];
+};
+
+__device__ __forceinline__ Nbrs neighbours(const Geom& g, int s) {
+  uint32_t r = (uint32_t)s;
+  uint32_t q = fdiv(r, g.dx);
+  int c[4];
+  c[0] = (int)(r - q * (uint32_t)g.L[0]);
+  r = q;
+  q = fdiv(r, g.dy);
+  c[1] = (int)(r - q * (uint32_t)g.L[1]);
+  r = q;
+  q = fdiv(r, g.dz);
+  c[2] = (int)(r - q * (uint32_t)g.L[2]);
+  c[3] = (int)q;
+  Nbrs n;
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    const int st = g.stride[mu];
+    const int span = st * (g.L[mu] - 1);
+    n.fwd[mu] = (c[mu] == g.L[mu] - 1) ? s - span : s + st;
+    n.bwd[mu] = (c[mu] == 0) ? s + span : s - st;
+  }
+  return n;
+}
+
+// Workgroup -> lattice tile. Workgroups are dealt round-robin to the 8 XCDs;
+// remapping gives each XCD one contiguous range of tiles so that the
+// neighbours a tile needs were recently fetched into the same XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int per = nb >> 3;
+  if (b < (per << 3)) return (b & 7) * per + (b >> 3);
+  return b;
+}
+
+// ----------------------------------------------------------- conversions
+
+__device__ __forceinline__ uint32_t f2bf_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return ((u >> 16) | 0x40u) & 0xffffu;
+  u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest even
+  return u >> 16;
+}
+__device__ __forceinline__ float bf_bits2f(uint32_t b) { return __uint_as_float(b << 16); }
+
+__device__ __forceinline__ uint32_t f2h_bits(float f) {
+  _Float16 h = (_Float16)f;          // v_cvt_f16_f32, round to nearest even
+  return (uint32_t)__builtin_bit_cast(uint16_t, h);
+}
+__device__ __forceinline__ float h_bits2f(uint32_t b) {
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)(b & 0xffffu));
+}
+
+template <int P> struct PrecTraits;
+template <> struct PrecTraits<P_F64> { using Real = double; static constexpr int spinor_words = 12; static constexpr int link_word_bytes = 16; };
+template <> struct PrecTraits<P_F32> { using Real = float;  static constexpr int spinor_words = 6;  static constexpr int link_word_bytes = 8; };
+template <> struct PrecTraits<P_BF16> { using Real = float; static constexpr int spinor_words = 3;  static constexpr int link_word_bytes = 4; };
+template <> struct PrecTraits<P_F16> { using Real = float;  static constexpr int spinor_words = 3;  static constexpr int link_word_bytes = 4; };
+
+__device__ __forceinline__ size_t word_index(int s, int nwords, int w) {
+  return ((size_t)(s >> 6) * nwords + w) * kSiteBlock + (s & 63);
+}
+
+// ------------------------------------------------- packed spinor access
+// A site's spinor in registers: 24 reals, index (spin * 3 + colour) * 2 + {re, im}.
+
+template <int P> struct PackedSpinor;
+
+template <> struct PackedSpinor<P_F64> {
+  using Real = double;
+  double2* data;
+  float* scale;  // unused
+  __device__ __forceinline__ void load(int s, Real v[24]) const {
+#pragma unroll
+    for (int w = 0; w < 12; ++w) {
+      double2 d = data[word_index(s, 12, w)];
+      v[2 * w] = d.x;
+      v[2 * w + 1] = d.y;
+    }
+  }
+  __device__ __forceinline__ void store(int s, const Real v[24]) const {
+#pragma unroll
+    for (int w = 0; w < 12; ++w) data[word_index(s, 12, w)] = make_double2(v[2 * w], v[2 * w + 1]);
+  }
+};
+
+template <> struct PackedSpinor<P_F32> {
+  using Real = float;
+  float4* data;
+  float* scale;
+  __device__ __forceinline__ void load(int s, Real v[24]) const {
+#pragma unroll
+    for (int w = 0; w < 6; ++w) {
+      float4 d = data[word_index(s, 6, w)];
+      v[4 * w] = d.x; v[4 * w + 1] = d.y; v[4 * w + 2] = d.z; v[4 * w + 3] = d.w;
+    }
+  }
+  __device__ __forceinline__ void store(int s, const Real v[24]) const {
+#pragma unroll
+    for (int w = 0; w < 6; ++w)
+      data[word_index(s, 6, w)] = make_float4(v[4 * w], v[4 * w + 1], v[4 * w + 2], v[4 * w + 3]);
+  }
+};
+
+template <> struct PackedSpinor<P_BF16> {
+  using Real = float;
+  uint4* data;
+  float* scale;
+  __device__ __forceinline__ void load(int s, Real v[24]) const {
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+      uint4 d = data[word_index(s, 3, w)];
+      uint32_t u[4] = {d.x, d.y, d.z, d.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        v[8 * w + 2 * k] = bf_bits2f(u[k] & 0xffffu);
+        v[8 * w + 2 * k + 1] = bf_bits2f(u[k] >> 16);
+      }
+    }
+  }
+  __device__ __forceinline__ void store(int s, const Real v[24]) const {
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+      uint32_t u[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) u[k] = f2bf_bits(v[8 * w + 2 * k]) | (f2bf_bits(v[8 * w + 2 * k + 1]) << 16);
+      data[word_index(s, 3, w)] = make_uint4(u[0], u[1], u[2], u[3]);
+    }
+  }
+};
+
+template <> struct PackedSpinor<P_F16> {
+  using Real = float;
+  uint4* data;
+  float* scale;   // per-site magnitude: stored value = v / scale, |stored| <= 1
+  __device__ __forceinline__ void load(int s, Real v[24]) const {
+    const float sc = scale[s];
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+      uint4 d = data[word_index(s, 3, w)];
+      uint32_t u[4] = {d.x, d.y, d.z, d.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        v[8 * w + 2 * k] = h_bits2f(u[k]) * sc;
+        v[8 * w + 2 * k + 1] = h_bits2f(u[k] >> 16) * sc;
+      }
+    }
+  }
+  __device__ __forceinline__ void store(int s, const Real v[24]) const {
+    float m = 0.f;
+#pragma unroll
+    for (int i = 0; i < 24; ++i) m = fmaxf(m, fabsf(v[i]));
+    const float inv = (m > 0.f) ? 1.0f / m : 0.f;
+    scale[s] = m;
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+      uint32_t u[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        u[k] = f2h_bits(v[8 * w + 2 * k] * inv) | (f2h_bits(v[8 * w + 2 * k + 1] * inv) << 16);
+      data[word_index(s, 3, w)] = make_uint4(u[0], u[1], u[2], u[3]);
+    }
+  }
+};
+
+// Canonical boundary layout: (Lt, Lz, Ly, Lx, 4, 3) complex128, AoS.
+struct CanonSpinor {
+  using Real = double;
+  double2* data;
+  __device__ __forceinline__ void load(int s, Real v[24]) const {
+    const double2* p = data + (size_t)s * 12;
+#pragma unroll
+    for (int w = 0; w < 12; ++w) {
+      double2 d = p[w];
+      v[2 * w] = d.x;
+      v[2 * w + 1] = d.y;
+    }
+  }
+  __device__ __forceinline__ void store(int s, const Real v[24]) const {
+    double2* p = data + (size_t)s * 12;
+#pragma unroll
+    for (int w = 0; w < 12; ++w) p[w] = make_double2(v[2 * w], v[2 * w + 1]);
+  }
+};
+
+// ---------------------------------------------------------- link access
+// A link in registers: 18 reals, index (row * 3 + col) * 2 + {re, im}.
+// The stencil asks for U_mu(x) through load_fwd(x, mu) and for U_mu(x - mu)
+// through load_bwd(x - mu, mu); accessors that read memory directly forward
+// both to load().
+#define WD_GAUGE_FORWARDERS                                                              \
+  template <typename R>                                                                  \
+  __device__ __forceinline__ void load_fwd(int s, int mu, R u[18]) const { load(s, mu, u); } \
+  template <typename R>                                                                  \
+  __device__ __forceinline__ void load_bwd(int s, int mu, R u[18]) const { load(s, mu, u); }
+
+template <int P> struct PackedGauge;
+
+template <> struct PackedGauge<P_F64> {
+  using Real = double;
+  WD_GAUGE_FORWARDERS
+  const double2* data;
+  __device__ __forceinline__ void load(int s, int mu, Real u[18]) const {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      double2 d = data[word_index(s, 36, mu * 9 + e)];
+      u[2 * e] = d.x;
+      u[2 * e + 1] = d.y;
+    }
+  }
+};
+
+template <> struct PackedGauge<P_F32> {
+  using Real = float;
+  WD_GAUGE_FORWARDERS
+  const float2* data;
+  __device__ __forceinline__ void load(int s, int mu, Real u[18]) const {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      float2 d = data[word_index(s, 36, mu * 9 + e)];
+      u[2 * e] = d.x;
+      u[2 * e + 1] = d.y;
+    }
+  }
+};
+
+template <> struct PackedGauge<P_BF16> {
+  using Real = float;
+  WD_GAUGE_FORWARDERS
+  const uint32_t* data;
+  __device__ __forceinline__ void load(int s, int mu, Real u[18]) const {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      uint32_t d = data[word_index(s, 36, mu * 9 + e)];
+      u[2 * e] = bf_bits2f(d & 0xffffu);
+      u[2 * e + 1] = bf_bits2f(d >> 16);
+    }
+  }
+};
+
+template <> struct PackedGauge<P_F16> {
+  using Real = float;
+  WD_GAUGE_FORWARDERS
+  const uint32_t* data;
+  __device__ __forceinline__ void load(int s, int mu, Real u[18]) const {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      uint32_t d = data[word_index(s, 36, mu * 9 + e)];
+      u[2 * e] = h_bits2f(d);
+      u[2 * e + 1] = h_bits2f(d >> 16);
+    }
+  }
+};
+
+// Canonical boundary layout: (4, Lt, Lz, Ly, Lx, 3, 3) complex128.
+struct CanonGauge {
+  using Real = double;
+  WD_GAUGE_FORWARDERS
+  const double2* data;
+  size_t V;
+  __device__ __forceinline__ void load(int s, int mu, Real u[18]) const {
+    const double2* p = data + ((size_t)mu * V + (size_t)s) * 9;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      double2 d = p[e];
+      u[2 * e] = d.x;
+      u[2 * e + 1] = d.y;
+    }
+  }
+};
+
+// Bytes of one packed field of V sites (padded volume).
+inline size_t spinor_bytes(int P, int Vpad) {
+  switch (P) {
+    case P_F64: return (size_t)Vpad * 192;
+    case P_F32: return (size_t)Vpad * 96;
+    default: return (size_t)Vpad * 48;
+  }
+}
+inline size_t spinor_scale_bytes(int P, int Vpad) { return P == P_F16 ? (size_t)Vpad * 4 : 0; }
+inline size_t gauge_bytes(int P, int Vpad) {
+  switch (P) {
+    case P_F64: return (size_t)Vpad * 4 * 9 * 16;
+    case P_F32: return (size_t)Vpad * 4 * 9 * 8;
+    default: return (size_t)Vpad * 4 * 9 * 4;
+  }
+}
+
+}  // namespace wd

@@ -1,0 +1,103 @@
+// Internal interface between the host driver (wd_api.cpp) and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "wd_common.hpp"
+
+namespace wd {
+
+// Device-resident solver state. All scalars of the CG recurrences live here,
+// are produced by the last workgroup of a reduction kernel, and are read by
+// the following kernels; the host reads a copy only when it polls.
+struct SolverState {
+  double rho;        // <r, r> of the current (inner) residual
+  double rho_prev;   // value before the last update (beta = rho / rho_prev)
+  double alpha;
+  double beta;
+  double tnorm;      // <t, t> = <p, D^+ D p>
+  double bnorm2;     // ||b'||^2
+  double stop2;      // (tol ||b'||)^2
+  double rho_true;   // ||b' - D^+ D x||^2 from the last FP64 recomputation
+  double rho_update; // rho right after the last reliable update (or at the start)
+  double delta2;     // mixed: also update once rho <= delta2 * rho_update
+  int iter;          // inner iterations completed
+  int status;        // 0 running, 1 converged, -3 breakdown, -4 NaN/Inf
+  int inner_done;    // mixed: inner residual reached the target; update pending
+  int last_update;   // iteration of the last reliable update
+  int interval;      // reliable-update interval (mixed)
+  int rel_updates;   // reliable updates performed
+  int hist_len;      // capacity of hist
+  int pad0;
+  unsigned int ticket;  // last-workgroup-done counter (returns to 0 after every reduction)
+  unsigned int pad1;
+  double* hist;      // per-iteration relative residual (device, in the workspace)
+};
+
+// When a kernel runs (decided identically by every workgroup from state that
+// only the kernel's own last workgroup may change).
+enum Gate : int {
+  G_ALWAYS = 0,   // unconditional
+  G_ITER = 1,     // a CG iteration: status == 0 and no reliable update pending
+  G_RELIABLE = 2, // reliable-update slot: status == 0 and (pending, interval reached, or
+                  //   residual reduced by delta since the last update)
+  G_FINAL = 3,    // final FP64 recomputation: unconditional
+};
+
+// What the last workgroup does with the reduced sum.
+enum Fin : int {
+  F_NONE = 0,
+  F_BNORM = 1,     // bnorm2 = sum; stop2 = tol^2 sum
+  F_RHO_INIT = 2,  // rho = sum (start of the solve)
+  F_ALPHA = 3,     // tnorm = sum; alpha = rho / tnorm
+  F_BETA = 4,      // rho_prev = rho; rho = sum; beta = rho / rho_prev; iter++; convergence test
+  F_RELIABLE = 5,  // rho_true = sum; converged? else rho = sum, beta = rho / rho_prev
+                   //   (beta = 0, a restart, if the true residual exceeds twice the iterated one)
+  F_TRUE = 6,      // rho_true = sum (final recomputation)
+};
+
+struct SpinorBuf {
+  void* data;
+  float* scale;   // FP16 storage only
+  int prec;
+};
+
+// ---- launchers (wd_kernels.hip). All asynchronous on `stream`.
+// Reset the state: stop2 = tol^2 (scaled by ||b'||^2 at F_BNORM), interval 0 = plain CG.
+void launch_init_state(SolverState* st, double tol, int interval, double delta, double* hist, int hist_len,
+                       hipStream_t s);
+// Continue after a failed final check: status = 0, rho = rho_true.
+void launch_restart(SolverState* st, hipStream_t s);
+void launch_pack_gauge(const Geom& g, const void* U_c128, int prec, void* out, hipStream_t s);
+void launch_pack_spinor(const Geom& g, const void* in, int io_c64, SpinorBuf out, hipStream_t s);
+void launch_unpack_spinor(const Geom& g, SpinorBuf in, void* out, int io_c64, hipStream_t s);
+void launch_convert(const Geom& g, SpinorBuf in, SpinorBuf out, int gate, SolverState* st, hipStream_t s);
+void launch_zero(const Geom& g, SpinorBuf v, int gate, SolverState* st, hipStream_t s);
+
+// out = D in (dagger = 0) or D^+ in on canonical complex128 fields.
+void launch_wilson_canonical(const Geom& g, const void* U, const void* in, void* out, double mass, int dagger,
+                             hipStream_t s);
+// out = D in / D^+ in on packed fields of one precision; optional reduction of ||out||^2.
+void launch_wilson_packed(const Geom& g, int prec, const void* U, SpinorBuf in, SpinorBuf out, double mass,
+                          int dagger, int gate, int fin, SolverState* st, double* partials, hipStream_t s);
+// q = D^+ t (never stored); r -= alpha q; x += alpha p; ||r||^2 -> F_BETA.
+void launch_cg_update(const Geom& g, int prec, const void* U, SpinorBuf t, SpinorBuf r, SpinorBuf p, SpinorBuf x,
+                      double mass, SolverState* st, double* partials, hipStream_t s);
+// out = low(b - D^+ t) with FP64 arithmetic on FP64 fields; ||b - D^+ t||^2 -> fin.
+void launch_residual(const Geom& g, const void* U64, SpinorBuf t64, SpinorBuf b64, SpinorBuf out, double mass,
+                     int gate, int fin, SolverState* st, double* partials, hipStream_t s);
+// p = r + beta p
+void launch_p_update(const Geom& g, SpinorBuf r, SpinorBuf p, SolverState* st, hipStream_t s);
+// x(FP64) += xhat; xhat = 0
+void launch_accumulate(const Geom& g, SpinorBuf x64, SpinorBuf xhat, int gate, SolverState* st, hipStream_t s);
+// ||v||^2 -> fin
+void launch_norm2(const Geom& g, SpinorBuf v, int gate, int fin, SolverState* st, double* partials, hipStream_t s);
+// Workspace of the batched persistent solver (wd_batched.hip).
+size_t batched_workspace_bytes(const Geom& g, int nrhs, int hist_len);
+
+// G(a, b) force on canonical complex128 spinors -> canonical complex128 links.
+void launch_force(const Geom& g, const void* a, const void* b, double coeff, int accumulate, void* F, hipStream_t s);
+
+}  // namespace wd

@@ -1,0 +1,618 @@
+// HIP kernels of the Wilson-Dirac library for gfx950: packing, the Wilson
+// stencil with fused solver epilogues, deterministic reductions, the CG
+// vector updates and the gauge-link force.
+#include <hip/hip_runtime.h>
+
+#include "wd_dslash.hpp"
+#include "wd_internal.hpp"
+
+namespace wd {
+
+// ------------------------------------------------------------ reductions
+
+// Sum over a 256-thread workgroup in a fixed order: butterfly within each
+// 64-lane wavefront, then the four wavefront sums in index order.
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double wsum[kBlock / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  if (lane == 0) wsum[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) t += wsum[i];
+  }
+  __syncthreads();
+  return t;   // valid in thread 0
+}
+
+__device__ __forceinline__ bool finite_d(double x) { return x - x == 0.0; }
+
+// Apply the end-of-reduction update to the solver state (one thread).
+__device__ void finalize(SolverState* st, int fin, double sum) {
+  switch (fin) {
+    case F_BNORM:
+      st->bnorm2 = sum;
+      st->stop2 = st->stop2 * sum;   // host stored tol^2 in stop2
+      break;
+    case F_RHO_INIT:
+      st->rho = sum;
+      st->rho_true = sum;
+      st->rho_update = sum;
+      if (!finite_d(sum)) st->status = -4;
+      else if (sum <= st->stop2) st->status = 1;
+      break;
+    case F_ALPHA:
+      st->tnorm = sum;
+      if (!finite_d(sum)) st->status = -4;
+      else if (sum <= 0.0) st->status = -3;
+      else st->alpha = st->rho / sum;
+      break;
+    case F_BETA: {
+      st->rho_prev = st->rho;
+      st->rho = sum;
+      st->iter += 1;
+      if (st->hist && st->iter <= st->hist_len) st->hist[st->iter - 1] = sqrt(sum / st->bnorm2);
+      if (!finite_d(sum)) {
+        st->status = -4;
+      } else {
+        st->beta = sum / st->rho_prev;
+        if (sum <= st->stop2) {
+          if (st->interval > 0) st->inner_done = 1;   // mixed: verify by a reliable update
+          else st->status = 1;
+        }
+      }
+      break;
+    }
+    case F_RELIABLE: {
+      const double iterated = st->rho;
+      st->rho_true = sum;
+      st->rho_update = sum;
+      st->rel_updates += 1;
+      st->last_update = st->iter;
+      st->inner_done = 0;
+      if (!finite_d(sum)) st->status = -4;
+      else if (sum <= st->stop2) st->status = 1;
+      else {
+        st->rho = sum;
+        // keep the search direction (beta from the recomputed residual) unless
+        // the low-precision recurrence has drifted far from the true residual
+        st->beta = (sum > 4.0 * iterated) ? 0.0 : sum / st->rho_prev;
+      }
+      break;
+    }
+    case F_TRUE:
+      st->rho_true = sum;
+      break;
+    default:
+      break;
+  }
+}
+
+// Last-workgroup-done reduction: every workgroup publishes its partial; the
+// workgroup that takes the last ticket sums all partials in index order
+// (deterministic), applies `fin` and re-arms the ticket.
+__device__ void grid_reduce(double v, double* partials, SolverState* st, int fin) {
+  __shared__ int am_last;
+  const double bs = block_sum(v);
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&partials[blockIdx.x], bs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned t = __hip_atomic_fetch_add(&st->ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    am_last = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!am_last) return;
+  __atomic_thread_fence(__ATOMIC_ACQUIRE);
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += kBlock)
+    acc += __hip_atomic_load(&partials[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const double total = block_sum(acc);
+  if (threadIdx.x == 0) {
+    finalize(st, fin, total);
+    __hip_atomic_store(&st->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__device__ __forceinline__ bool gate_open(const SolverState* st, int gate) {
+  if (gate == G_ALWAYS || gate == G_FINAL) return true;
+  const int status = st->status;
+  if (gate == G_ITER) return status == 0 && st->inner_done == 0;
+  // G_RELIABLE
+  return status == 0 && (st->inner_done != 0 || st->iter - st->last_update >= st->interval ||
+                         st->rho <= st->delta2 * st->rho_update);
+}
+
+// ------------------------------------------------------- spinor dispatch
+
+template <int P> __device__ __forceinline__ PackedSpinor<P> spinor_of(const SpinorBuf& b) {
+  PackedSpinor<P> s;
+  s.data = reinterpret_cast<decltype(s.data)>(b.data);
+  s.scale = b.scale;
+  return s;
+}
+template <int P> __device__ __forceinline__ PackedGauge<P> gauge_of(const void* p) {
+  PackedGauge<P> u;
+  u.data = reinterpret_cast<decltype(u.data)>(p);
+  return u;
+}
+
+// ---------------------------------------------------------------- packing
+
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_pack_gauge(Geom g, const double2* __restrict__ U, void* out) {
+  const int s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= g.V) return;
+  for (int mu = 0; mu < 4; ++mu) {
+    const double2* src = U + ((size_t)mu * g.V + s) * 9;
+    for (int e = 0; e < 9; ++e) {
+      const double2 d = src[e];
+      const size_t w = word_index(s, 36, mu * 9 + e);
+      if constexpr (P == P_F64) reinterpret_cast<double2*>(out)[w] = d;
+      else if constexpr (P == P_F32) reinterpret_cast<float2*>(out)[w] = make_float2((float)d.x, (float)d.y);
+      else if constexpr (P == P_BF16)
+        reinterpret_cast<uint32_t*>(out)[w] = f2bf_bits((float)d.x) | (f2bf_bits((float)d.y) << 16);
+      else
+        reinterpret_cast<uint32_t*>(out)[w] = f2h_bits((float)d.x) | (f2h_bits((float)d.y) << 16);
+    }
+  }
+}
+
+template <int P, typename IO>
+__global__ __launch_bounds__(kBlock) void k_pack_spinor(Geom g, const IO* __restrict__ in, SpinorBuf out) {
+  const int s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= g.V) return;
+  using R = typename PackedSpinor<P>::Real;
+  R v[24];
+  const IO* p = in + (size_t)s * 12;
+#pragma unroll
+  for (int i = 0; i < 12; ++i) {
+    v[2 * i] = (R)p[i].x;
+    v[2 * i + 1] = (R)p[i].y;
+  }
+  spinor_of<P>(out).store(s, v);
+}
+
+template <int P, typename IO>
+__global__ __launch_bounds__(kBlock) void k_unpack_spinor(Geom g, SpinorBuf in, IO* __restrict__ out) {
+  const int s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= g.V) return;
+  using R = typename PackedSpinor<P>::Real;
+  R v[24];
+  spinor_of<P>(in).load(s, v);
+  IO* p = out + (size_t)s * 12;
+#pragma unroll
+  for (int i = 0; i < 12; ++i) {
+    IO d;
+    d.x = v[2 * i];
+    d.y = v[2 * i + 1];
+    p[i] = d;
+  }
+}
+
+template <int PA, int PB>
+__global__ __launch_bounds__(kBlock) void k_convert(Geom g, SpinorBuf in, SpinorBuf out, int gate,
+                                                    const SolverState* st) {
+  if (!gate_open(st, gate)) return;
+  const int s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= g.V) return;
+  typename PackedSpinor<PA>::Real a[24];
+  typename PackedSpinor<PB>::Real b[24];
+  spinor_of<PA>(in).load(s, a);
+#pragma unroll
+  for (int i = 0; i < 24; ++i) b[i] = (typename PackedSpinor<PB>::Real)a[i];
+  spinor_of<PB>(out).store(s, b);
+}
+
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_zero(Geom g, SpinorBuf v, int gate, const SolverState* st) {
+  if (!gate_open(st, gate)) return;
+  const int s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= g.V) return;
+  typename PackedSpinor<P>::Real z[24];
+#pragma unroll
+  for (int i = 0; i < 24; ++i) z[i] = 0;
+  spinor_of<P>(v).store(s, z);
+}
+
+// -------------------------------------------------------- Wilson operator
+
+template <bool DAG>
+__global__ __launch_bounds__(kBlock) void k_wilson_canonical(Geom g, CanonGauge U, CanonSpinor in, CanonSpinor out,
+                                                             double diag) {
+  const int s = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (s >= g.V) return;
+  const Nbrs nb = neighbours(g, s);
+  double o[24];
+  wilson_site<DAG>(U, in, s, nb, diag, o);
+  out.store(s, o);
+}
+
+template <int P, bool DAG>
+__global__ __launch_bounds__(kBlock) void k_wilson_packed(Geom g, const void* U, SpinorBuf in, SpinorBuf out,
+                                                          double diag, int gate, int fin, SolverState* st,
+                                                          double* partials) {
+  if (!gate_open(st, gate)) return;
+  using R = typename PackedSpinor<P>::Real;
+  const int s = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  double n2 = 0.0;
+  if (s < g.V) {
+    const Nbrs nb = neighbours(g, s);
+    R o[24];
+    wilson_site<DAG>(gauge_of<P>(U), spinor_of<P>(in), s, nb, (R)diag, o);
+    spinor_of<P>(out).store(s, o);
+    if (fin != F_NONE) {
+#pragma unroll
+      for (int i = 0; i < 24; ++i) n2 += (double)o[i] * (double)o[i];
+    }
+  }
+  if (fin != F_NONE) grid_reduce(n2, partials, st, fin);
+}
+
+// q = D^+ t at site s; r -= alpha q; x += alpha p; reduce ||r||^2 (of the stored r).
+template <int P, int PX>
+__global__ __launch_bounds__(kBlock) void k_cg_update(Geom g, const void* U, SpinorBuf t, SpinorBuf r, SpinorBuf p,
+                                                      SpinorBuf x, double diag, SolverState* st, double* partials) {
+  if (!gate_open(st, G_ITER)) return;
+  using R = typename PackedSpinor<P>::Real;
+  using RX = typename PackedSpinor<PX>::Real;
+  const int s = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const double alpha = st->alpha;
+  double n2 = 0.0;
+  if (s < g.V) {
+    const Nbrs nb = neighbours(g, s);
+    R q[24];
+    wilson_site<true>(gauge_of<P>(U), spinor_of<P>(t), s, nb, (R)diag, q);
+    R rv[24], pv[24];
+    RX xv[24];
+    const auto rs = spinor_of<P>(r);
+    rs.load(s, rv);
+    spinor_of<P>(p).load(s, pv);
+    spinor_of<PX>(x).load(s, xv);
+    const R a = (R)alpha;
+#pragma unroll
+    for (int i = 0; i < 24; ++i) {
+      rv[i] = fma(-a, q[i], rv[i]);
+      xv[i] = fma((RX)alpha, (RX)pv[i], xv[i]);
+    }
+    rs.store(s, rv);
+    spinor_of<PX>(x).store(s, xv);
+    if constexpr (P == P_F64 || P == P_F32) {
+#pragma unroll
+      for (int i = 0; i < 24; ++i) n2 += (double)rv[i] * (double)rv[i];
+    } else {
+      // the norm of what the next iteration will read
+      rs.load(s, rv);
+#pragma unroll
+      for (int i = 0; i < 24; ++i) n2 += (double)rv[i] * (double)rv[i];
+    }
+  }
+  grid_reduce(n2, partials, st, F_BETA);
+}
+
+// out = low(b - D^+ t) in FP64 arithmetic (t, b and links FP64); reduce the FP64 norm.
+template <int PO>
+__global__ __launch_bounds__(kBlock) void k_residual(Geom g, const void* U64, SpinorBuf t64, SpinorBuf b64,
+                                                     SpinorBuf out, double diag, int gate, int fin, SolverState* st,
+                                                     double* partials) {
+  if (!gate_open(st, gate)) return;
+  const int s = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  double n2 = 0.0;
+  if (s < g.V) {
+    const Nbrs nb = neighbours(g, s);
+    double q[24], b[24];
+    wilson_site<true>(gauge_of<P_F64>(U64), spinor_of<P_F64>(t64), s, nb, diag, q);
+    spinor_of<P_F64>(b64).load(s, b);
+    typename PackedSpinor<PO>::Real o[24];
+#pragma unroll
+    for (int i = 0; i < 24; ++i) {
+      const double d = b[i] - q[i];
+      n2 += d * d;
+      o[i] = (typename PackedSpinor<PO>::Real)d;
+    }
+    spinor_of<PO>(out).store(s, o);
+  }
+  grid_reduce(n2, partials, st, fin);
+}
+
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_p_update(Geom g, SpinorBuf r, SpinorBuf p, const SolverState* st) {
+  if (!gate_open(st, G_ITER)) return;
+  using R = typename PackedSpinor<P>::Real;
+  const int s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= g.V) return;
+  const R beta = (R)st->beta;
+  R rv[24], pv[24];
+  spinor_of<P>(r).load(s, rv);
+  spinor_of<P>(p).load(s, pv);
+#pragma unroll
+  for (int i = 0; i < 24; ++i) pv[i] = fma(beta, pv[i], rv[i]);
+  spinor_of<P>(p).store(s, pv);
+}
+
+template <int PX>
+__global__ __launch_bounds__(kBlock) void k_accumulate(Geom g, SpinorBuf x64, SpinorBuf xhat, int gate,
+                                                       const SolverState* st) {
+  if (!gate_open(st, gate)) return;
+  const int s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= g.V) return;
+  double xv[24];
+  typename PackedSpinor<PX>::Real hv[24];
+  spinor_of<P_F64>(x64).load(s, xv);
+  spinor_of<PX>(xhat).load(s, hv);
+#pragma unroll
+  for (int i = 0; i < 24; ++i) {
+    xv[i] += (double)hv[i];
+    hv[i] = 0;
+  }
+  spinor_of<P_F64>(x64).store(s, xv);
+  spinor_of<PX>(xhat).store(s, hv);
+}
+
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_norm2(Geom g, SpinorBuf v, int gate, int fin, SolverState* st,
+                                                  double* partials) {
+  if (!gate_open(st, gate)) return;
+  const int s = blockIdx.x * kBlock + threadIdx.x;
+  double n2 = 0.0;
+  if (s < g.V) {
+    typename PackedSpinor<P>::Real a[24];
+    spinor_of<P>(v).load(s, a);
+#pragma unroll
+    for (int i = 0; i < 24; ++i) n2 += (double)a[i] * (double)a[i];
+  }
+  grid_reduce(n2, partials, st, fin);
+}
+
+// ------------------------------------------------------------------ force
+// G(a, b)_mu(x) = 1/2 sum_spin [ ((1 - g_mu) a(x)) (x) b(x+mu)^* + b(x) (x) ((1 + g_mu) a(x+mu))^* ]
+// In half-spinor form: (1 - g) a = [h; -A^+ h] with h = a_up - A a_dn, so
+//   sum_spin ((1-g)a)_s (x) b_s^* = h (x) (b_up - A b_dn)^*  (two colour outer products),
+// and likewise (1 + g): sum_spin b_s (x) ((1+g)a)_s^* = (b_up + A b_dn) (x) h'^*.
+
+template <int MU>
+__device__ __forceinline__ void force_dir(const double a0[24], const double b0[24], const double a1[24],
+                                          const double b1[24], double F[18]) {
+  double h1[12], k1[12], h2[12], k2[12];
+  project<MU, -1>(a0, h1);   // (1 - g) a(x), upper half
+  project<MU, -1>(b1, k1);   // matching combination of b(x + mu)
+  project<MU, +1>(b0, h2);   // (1 + g) b(x)
+  project<MU, +1>(a1, k2);   // (1 + g) a(x + mu)
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double re = 0.0, im = 0.0;
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        // u_i conj(v_j)
+        const double ur = h1[(k * 3 + i) * 2], ui = h1[(k * 3 + i) * 2 + 1];
+        const double vr = k1[(k * 3 + j) * 2], vi = k1[(k * 3 + j) * 2 + 1];
+        re += ur * vr + ui * vi;
+        im += ui * vr - ur * vi;
+        const double wr = h2[(k * 3 + i) * 2], wi = h2[(k * 3 + i) * 2 + 1];
+        const double zr = k2[(k * 3 + j) * 2], zi = k2[(k * 3 + j) * 2 + 1];
+        re += wr * zr + wi * zi;
+        im += wi * zr - wr * zi;
+      }
+      F[(i * 3 + j) * 2] = re;
+      F[(i * 3 + j) * 2 + 1] = im;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_force(Geom g, CanonSpinor a, CanonSpinor b, double coeff, int accumulate,
+                                                  double2* __restrict__ F) {
+  const int s = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (s >= g.V) return;
+  const Nbrs nb = neighbours(g, s);
+  double a0[24], b0[24], a1[24], b1[24], f[18];
+  a.load(s, a0);
+  b.load(s, b0);
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    a.load(nb.fwd[mu], a1);
+    b.load(nb.fwd[mu], b1);
+    switch (mu) {
+      case 0: force_dir<0>(a0, b0, a1, b1, f); break;
+      case 1: force_dir<1>(a0, b0, a1, b1, f); break;
+      case 2: force_dir<2>(a0, b0, a1, b1, f); break;
+      default: force_dir<3>(a0, b0, a1, b1, f); break;
+    }
+    double2* dst = F + ((size_t)mu * g.V + s) * 9;
+    const double c = 0.5 * coeff;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      double2 v = make_double2(c * f[2 * e], c * f[2 * e + 1]);
+      if (accumulate) {
+        const double2 o = dst[e];
+        v.x += o.x;
+        v.y += o.y;
+      }
+      dst[e] = v;
+    }
+  }
+}
+
+__global__ void k_init_state(SolverState* st, double tol, int interval, double delta, double* hist,
+                             int hist_len) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  SolverState z{};
+  z.stop2 = tol * tol;
+  z.interval = interval;
+  z.delta2 = delta * delta;
+  z.hist = hist;
+  z.hist_len = hist_len;
+  z.alpha = 0.0;
+  z.beta = 0.0;
+  *st = z;
+}
+
+__global__ void k_restart(SolverState* st) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  st->status = 0;
+  st->inner_done = 0;
+  st->rho = st->rho_true;
+}
+
+// ============================================================= launchers
+
+void launch_init_state(SolverState* st, double tol, int interval, double delta, double* hist, int hist_len,
+                       hipStream_t s) {
+  k_init_state<<<1, 64, 0, s>>>(st, tol, interval, delta, hist, hist_len);
+}
+
+void launch_restart(SolverState* st, hipStream_t s) { k_restart<<<1, 64, 0, s>>>(st); }
+
+static inline dim3 grid_of(const Geom& g) { return dim3(g.nblocks); }
+
+void launch_pack_gauge(const Geom& g, const void* U, int prec, void* out, hipStream_t s) {
+  const double2* u = static_cast<const double2*>(U);
+  switch (prec) {
+    case P_F64: k_pack_gauge<P_F64><<<grid_of(g), kBlock, 0, s>>>(g, u, out); break;
+    case P_F32: k_pack_gauge<P_F32><<<grid_of(g), kBlock, 0, s>>>(g, u, out); break;
+    case P_BF16: k_pack_gauge<P_BF16><<<grid_of(g), kBlock, 0, s>>>(g, u, out); break;
+    default: k_pack_gauge<P_F16><<<grid_of(g), kBlock, 0, s>>>(g, u, out); break;
+  }
+}
+
+template <typename IO>
+static void pack_spinor_io(const Geom& g, const IO* in, SpinorBuf out, hipStream_t s) {
+  switch (out.prec) {
+    case P_F64: k_pack_spinor<P_F64, IO><<<grid_of(g), kBlock, 0, s>>>(g, in, out); break;
+    case P_F32: k_pack_spinor<P_F32, IO><<<grid_of(g), kBlock, 0, s>>>(g, in, out); break;
+    case P_BF16: k_pack_spinor<P_BF16, IO><<<grid_of(g), kBlock, 0, s>>>(g, in, out); break;
+    default: k_pack_spinor<P_F16, IO><<<grid_of(g), kBlock, 0, s>>>(g, in, out); break;
+  }
+}
+
+void launch_pack_spinor(const Geom& g, const void* in, int io_c64, SpinorBuf out, hipStream_t s) {
+  if (io_c64) pack_spinor_io(g, static_cast<const float2*>(in), out, s);
+  else pack_spinor_io(g, static_cast<const double2*>(in), out, s);
+}
+
+template <typename IO>
+static void unpack_spinor_io(const Geom& g, SpinorBuf in, IO* out, hipStream_t s) {
+  switch (in.prec) {
+    case P_F64: k_unpack_spinor<P_F64, IO><<<grid_of(g), kBlock, 0, s>>>(g, in, out); break;
+    case P_F32: k_unpack_spinor<P_F32, IO><<<grid_of(g), kBlock, 0, s>>>(g, in, out); break;
+    case P_BF16: k_unpack_spinor<P_BF16, IO><<<grid_of(g), kBlock, 0, s>>>(g, in, out); break;
+    default: k_unpack_spinor<P_F16, IO><<<grid_of(g), kBlock, 0, s>>>(g, in, out); break;
+  }
+}
+
+void launch_unpack_spinor(const Geom& g, SpinorBuf in, void* out, int io_c64, hipStream_t s) {
+  if (io_c64) unpack_spinor_io(g, in, static_cast<float2*>(out), s);
+  else unpack_spinor_io(g, in, static_cast<double2*>(out), s);
+}
+
+template <int PA>
+static void convert_from(const Geom& g, SpinorBuf in, SpinorBuf out, int gate, SolverState* st, hipStream_t s) {
+  switch (out.prec) {
+    case P_F64: k_convert<PA, P_F64><<<grid_of(g), kBlock, 0, s>>>(g, in, out, gate, st); break;
+    case P_F32: k_convert<PA, P_F32><<<grid_of(g), kBlock, 0, s>>>(g, in, out, gate, st); break;
+    case P_BF16: k_convert<PA, P_BF16><<<grid_of(g), kBlock, 0, s>>>(g, in, out, gate, st); break;
+    default: k_convert<PA, P_F16><<<grid_of(g), kBlock, 0, s>>>(g, in, out, gate, st); break;
+  }
+}
+
+void launch_convert(const Geom& g, SpinorBuf in, SpinorBuf out, int gate, SolverState* st, hipStream_t s) {
+  switch (in.prec) {
+    case P_F64: convert_from<P_F64>(g, in, out, gate, st, s); break;
+    case P_F32: convert_from<P_F32>(g, in, out, gate, st, s); break;
+    case P_BF16: convert_from<P_BF16>(g, in, out, gate, st, s); break;
+    default: convert_from<P_F16>(g, in, out, gate, st, s); break;
+  }
+}
+
+void launch_zero(const Geom& g, SpinorBuf v, int gate, SolverState* st, hipStream_t s) {
+  switch (v.prec) {
+    case P_F64: k_zero<P_F64><<<grid_of(g), kBlock, 0, s>>>(g, v, gate, st); break;
+    case P_F32: k_zero<P_F32><<<grid_of(g), kBlock, 0, s>>>(g, v, gate, st); break;
+    case P_BF16: k_zero<P_BF16><<<grid_of(g), kBlock, 0, s>>>(g, v, gate, st); break;
+    default: k_zero<P_F16><<<grid_of(g), kBlock, 0, s>>>(g, v, gate, st); break;
+  }
+}
+
+void launch_wilson_canonical(const Geom& g, const void* U, const void* in, void* out, double mass, int dagger,
+                             hipStream_t s) {
+  CanonGauge u{static_cast<const double2*>(U), (size_t)g.V};
+  CanonSpinor i{const_cast<double2*>(static_cast<const double2*>(in))};
+  CanonSpinor o{static_cast<double2*>(out)};
+  if (dagger) k_wilson_canonical<true><<<grid_of(g), kBlock, 0, s>>>(g, u, i, o, mass + 4.0);
+  else k_wilson_canonical<false><<<grid_of(g), kBlock, 0, s>>>(g, u, i, o, mass + 4.0);
+}
+
+template <int P>
+static void wilson_packed_p(const Geom& g, const void* U, SpinorBuf in, SpinorBuf out, double mass, int dagger,
+                            int gate, int fin, SolverState* st, double* partials, hipStream_t s) {
+  if (dagger)
+    k_wilson_packed<P, true><<<grid_of(g), kBlock, 0, s>>>(g, U, in, out, mass + 4.0, gate, fin, st, partials);
+  else
+    k_wilson_packed<P, false><<<grid_of(g), kBlock, 0, s>>>(g, U, in, out, mass + 4.0, gate, fin, st, partials);
+}
+
+void launch_wilson_packed(const Geom& g, int prec, const void* U, SpinorBuf in, SpinorBuf out, double mass,
+                          int dagger, int gate, int fin, SolverState* st, double* partials, hipStream_t s) {
+  switch (prec) {
+    case P_F64: wilson_packed_p<P_F64>(g, U, in, out, mass, dagger, gate, fin, st, partials, s); break;
+    case P_F32: wilson_packed_p<P_F32>(g, U, in, out, mass, dagger, gate, fin, st, partials, s); break;
+    case P_BF16: wilson_packed_p<P_BF16>(g, U, in, out, mass, dagger, gate, fin, st, partials, s); break;
+    default: wilson_packed_p<P_F16>(g, U, in, out, mass, dagger, gate, fin, st, partials, s); break;
+  }
+}
+
+void launch_cg_update(const Geom& g, int prec, const void* U, SpinorBuf t, SpinorBuf r, SpinorBuf p, SpinorBuf x,
+                      double mass, SolverState* st, double* partials, hipStream_t s) {
+  const double diag = mass + 4.0;
+  switch (prec) {
+    case P_F64: k_cg_update<P_F64, P_F64><<<grid_of(g), kBlock, 0, s>>>(g, U, t, r, p, x, diag, st, partials); break;
+    case P_F32: k_cg_update<P_F32, P_F32><<<grid_of(g), kBlock, 0, s>>>(g, U, t, r, p, x, diag, st, partials); break;
+    case P_BF16: k_cg_update<P_BF16, P_F32><<<grid_of(g), kBlock, 0, s>>>(g, U, t, r, p, x, diag, st, partials); break;
+    default: k_cg_update<P_F16, P_F32><<<grid_of(g), kBlock, 0, s>>>(g, U, t, r, p, x, diag, st, partials); break;
+  }
+}
+
+void launch_residual(const Geom& g, const void* U64, SpinorBuf t64, SpinorBuf b64, SpinorBuf out, double mass,
+                     int gate, int fin, SolverState* st, double* partials, hipStream_t s) {
+  const double diag = mass + 4.0;
+  switch (out.prec) {
+    case P_F64: k_residual<P_F64><<<grid_of(g), kBlock, 0, s>>>(g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
+    case P_F32: k_residual<P_F32><<<grid_of(g), kBlock, 0, s>>>(g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
+    case P_BF16: k_residual<P_BF16><<<grid_of(g), kBlock, 0, s>>>(g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
+    default: k_residual<P_F16><<<grid_of(g), kBlock, 0, s>>>(g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
+  }
+}
+
+void launch_p_update(const Geom& g, SpinorBuf r, SpinorBuf p, SolverState* st, hipStream_t s) {
+  switch (p.prec) {
+    case P_F64: k_p_update<P_F64><<<grid_of(g), kBlock, 0, s>>>(g, r, p, st); break;
+    case P_F32: k_p_update<P_F32><<<grid_of(g), kBlock, 0, s>>>(g, r, p, st); break;
+    case P_BF16: k_p_update<P_BF16><<<grid_of(g), kBlock, 0, s>>>(g, r, p, st); break;
+    default: k_p_update<P_F16><<<grid_of(g), kBlock, 0, s>>>(g, r, p, st); break;
+  }
+}
+
+void launch_accumulate(const Geom& g, SpinorBuf x64, SpinorBuf xhat, int gate, SolverState* st, hipStream_t s) {
+  if (xhat.prec == P_F64) k_accumulate<P_F64><<<grid_of(g), kBlock, 0, s>>>(g, x64, xhat, gate, st);
+  else k_accumulate<P_F32><<<grid_of(g), kBlock, 0, s>>>(g, x64, xhat, gate, st);
+}
+
+void launch_norm2(const Geom& g, SpinorBuf v, int gate, int fin, SolverState* st, double* partials, hipStream_t s) {
+  switch (v.prec) {
+    case P_F64: k_norm2<P_F64><<<grid_of(g), kBlock, 0, s>>>(g, v, gate, fin, st, partials); break;
+    case P_F32: k_norm2<P_F32><<<grid_of(g), kBlock, 0, s>>>(g, v, gate, fin, st, partials); break;
+    case P_BF16: k_norm2<P_BF16><<<grid_of(g), kBlock, 0, s>>>(g, v, gate, fin, st, partials); break;
+    default: k_norm2<P_F16><<<grid_of(g), kBlock, 0, s>>>(g, v, gate, fin, st, partials); break;
+  }
+}
+
+void launch_force(const Geom& g, const void* a, const void* b, double coeff, int accumulate, void* F, hipStream_t s) {
+  CanonSpinor ca{const_cast<double2*>(static_cast<const double2*>(a))};
+  CanonSpinor cb{const_cast<double2*>(static_cast<const double2*>(b))};
+  k_force<<<grid_of(g), kBlock, 0, s>>>(g, ca, cb, coeff, accumulate, static_cast<double2*>(F));
+}
+
+}  // namespace wd

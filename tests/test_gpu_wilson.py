@@ -1,0 +1,98 @@
+"""GPU parity of the Wilson operator kernels against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import fieldgen
+import oracle
+from gpu_util import log, rel, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+wd = pytest.importorskip("paper_2001_05218_amd")
+
+# tiny, extent-2 directions, non-cubic, a ragged last workgroup, several workgroups
+DIMS = [(2, 2, 2, 2), (4, 4, 4, 4), (3, 2, 4, 2), (6, 4, 8, 2), (5, 3, 7, 4), (8, 8, 8, 16), (16, 16, 16, 32)]
+
+
+@pytest.mark.parametrize("dagger", [False, True])
+@pytest.mark.parametrize("dims", DIMS)
+def test_wilson_apply_fp64_parity(dims, dagger):
+    log(f"wilson_apply dims={dims} dagger={dagger}")
+    U = fieldgen.gauge_field(dims, "haar", 11)
+    psi = fieldgen.gaussian_spinor(dims, 12)
+    out = to_np(wd.wilson_apply(to_dev(U), to_dev(psi), 0.1, dagger=dagger))
+    ref = (oracle.wilson_Ddag if dagger else oracle.wilson_D)(U, psi, 0.1)
+    assert rel(out, ref) <= 1e-12
+    # element-wise against the largest component
+    assert np.abs(out - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (5, 3, 7, 4), (16, 16, 16, 32)])
+def test_wilson_apply_packed_fp64_parity(dims):
+    log(f"wilson_apply_packed f64 dims={dims}")
+    U = fieldgen.gauge_field(dims, "near_identity", 21, eps=0.3)
+    psi = fieldgen.gaussian_spinor(dims, 22)
+    Ut, pt = to_dev(U), to_dev(psi)
+    Up = wd.pack_gauge(Ut, "f64")
+    pin = wd.pack_spinor(pt, "f64")
+    for dagger in (False, True):
+        pout = wd.empty_packed_spinor(dims, "f64", pt.device)
+        wd.wilson_apply_packed(Up, pin, pout, dims, 0.05, "f64", dagger)
+        out = to_np(wd.unpack_spinor(pout, dims, "f64"))
+        ref = (oracle.wilson_Ddag if dagger else oracle.wilson_D)(U, psi, 0.05)
+        assert rel(out, ref) <= 1e-12
+
+
+def test_pack_roundtrip_exact_fp64():
+    dims = (5, 3, 7, 4)
+    psi = fieldgen.gaussian_spinor(dims, 3)
+    back = to_np(wd.unpack_spinor(wd.pack_spinor(to_dev(psi), "f64"), dims, "f64"))
+    assert np.array_equal(back, psi)
+
+
+@pytest.mark.parametrize("prec,bound", [("f32", 1e-6), ("bf16", 8e-3), ("f16", 1.5e-3)])
+def test_pack_roundtrip_low_precision(prec, bound):
+    dims = (5, 3, 7, 4)
+    psi = fieldgen.gaussian_spinor(dims, 3)
+    back = to_np(wd.unpack_spinor(wd.pack_spinor(to_dev(psi), prec), dims, prec))
+    assert rel(back, psi) <= bound
+
+
+@pytest.mark.parametrize("prec,bound", [("f32", 2e-6), ("bf16", 1.5e-2), ("f16", 3e-3)])
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 8, 2)])
+def test_wilson_apply_packed_low_precision(dims, prec, bound):
+    log(f"wilson_apply_packed {prec} dims={dims}")
+    U = fieldgen.gauge_field(dims, "haar", 31)
+    psi = fieldgen.gaussian_spinor(dims, 32)
+    Ut, pt = to_dev(U), to_dev(psi)
+    Up = wd.pack_gauge(Ut, prec)
+    pin = wd.pack_spinor(pt, prec)
+    pout = wd.empty_packed_spinor(dims, prec, pt.device)
+    wd.wilson_apply_packed(Up, pin, pout, dims, 0.1, prec, False)
+    out = to_np(wd.unpack_spinor(pout, dims, prec))
+    assert rel(out, oracle.wilson_D(U, psi, 0.1)) <= bound
+
+
+def test_full_size_sampled_sites_32x32x32x64():
+    # the benchmark's lattice: check sampled sites one by one with the oracle
+    dims = (32, 32, 32, 64)
+    log("wilson_apply 32^3x64 sampled")
+    U = fieldgen.gauge_field(dims, "near_identity", 200105238, eps=0.3)
+    psi = fieldgen.gaussian_spinor(dims, 200105239)
+    out = to_np(wd.wilson_apply(to_dev(U), to_dev(psi), 0.02))
+    rng = np.random.default_rng(0)
+    sites = [(0, 0, 0, 0), (31, 31, 31, 63), (31, 0, 15, 32)] + [
+        tuple(int(rng.integers(0, L)) for L in dims) for _ in range(29)]
+    ref = oracle.wilson_D_sites(U, psi, 0.02, sites)
+    for k, (x, y, z, t) in enumerate(sites):
+        assert np.abs(out[t, z, y, x] - ref[k]).max() <= 1e-12 * np.abs(ref[k]).max()
+
+
+def test_adjoint_identity_on_gpu():
+    dims = (8, 8, 8, 16)
+    U = to_dev(fieldgen.gauge_field(dims, "haar", 41))
+    a = to_dev(fieldgen.gaussian_spinor(dims, 42))
+    b = to_dev(fieldgen.gaussian_spinor(dims, 43))
+    lhs = (a.conj() * wd.wilson_apply(U, b, 0.1)).sum().item()
+    rhs = (wd.wilson_apply(U, a, 0.1, dagger=True).conj() * b).sum().item()
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)

@@ -1,0 +1,150 @@
+"""The C-ABI library loads and exports what include/wilson.h declares, and
+rejects bad arguments before any device work (CPU only: no kernel runs)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2001_05218_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return _lib.load()
+
+
+def test_every_declared_function_is_exported(lib):
+    names = _lib.header_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_signatures_cover_header():
+    assert set(_lib.header_functions()) == set(_lib.SIGNATURES)
+
+
+def test_required_boundary_calls_present():
+    for n in ("wilson_apply", "wilson_apply_dagger", "cg_solve", "cg_solve_batched", "wilson_force"):
+        assert n in _lib.header_functions()
+
+
+def test_struct_layouts_match_header():
+    # sizes of the structs as laid out by a C compiler for the header
+    assert ctypes.sizeof(_lib.WdLattice) == 16
+    assert ctypes.sizeof(_lib.WdCgParams) == 48
+    assert ctypes.sizeof(_lib.WdCgResult) == 40
+
+
+def _lat(dims):
+    return ctypes.byref(_lib.lattice(dims))
+
+
+def _params(**kw):
+    p = _lib.WdCgParams()
+    p.tol = kw.get("tol", 1e-10)
+    p.max_iter = kw.get("max_iter", 100)
+    p.inner_prec = kw.get("inner_prec", 0)
+    p.reliable_interval = kw.get("reliable_interval", 50)
+    p.rhs_mode = kw.get("rhs_mode", 0)
+    p.io_dtype = kw.get("io_dtype", 0)
+    p.zero_guess = 1
+    p.history_len = kw.get("history_len", 0)
+    return p
+
+
+BAD_DIMS = [(1, 4, 4, 4), (4, 4, 4, 0), (4, -2, 4, 4), (2048, 2048, 2048, 2)]
+
+
+@pytest.mark.parametrize("dims", BAD_DIMS)
+def test_apply_rejects_bad_lattice(lib, dims):
+    rc = lib.wilson_apply(_lat(dims), 0.1, 1, 2, 3, None)
+    assert rc == _lib.WD_ERR_INVALID
+    assert "lattice" in _lib.last_error()
+
+
+def test_apply_rejects_null_and_alias(lib):
+    assert lib.wilson_apply(None, 0.1, 1, 2, 3, None) == _lib.WD_ERR_INVALID
+    assert lib.wilson_apply(_lat((4, 4, 4, 4)), 0.1, None, 2, 3, None) == _lib.WD_ERR_INVALID
+    assert lib.wilson_apply_dagger(_lat((4, 4, 4, 4)), 0.1, 1, 2, 2, None) == _lib.WD_ERR_INVALID
+    assert "alias" in _lib.last_error()
+    assert lib.wilson_apply(_lat((4, 4, 4, 4)), float("nan"), 1, 2, 3, None) == _lib.WD_ERR_INVALID
+
+
+def test_force_rejects_bad_args(lib):
+    assert lib.wilson_force(_lat((4, 4, 4, 4)), None, 2, 1.0, 0, 3, None) == _lib.WD_ERR_INVALID
+    assert lib.wilson_force(_lat((4, 1, 4, 4)), 1, 2, 1.0, 0, 3, None) == _lib.WD_ERR_INVALID
+    assert lib.wilson_force(_lat((4, 4, 4, 4)), 1, 2, float("inf"), 0, 3, None) == _lib.WD_ERR_INVALID
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(tol=0.0), "tol"), (dict(tol=-1.0), "tol"), (dict(max_iter=0), "max_iter"),
+    (dict(inner_prec=7), "inner_prec"), (dict(rhs_mode=3), "rhs_mode"), (dict(io_dtype=5), "io_dtype"),
+    (dict(reliable_interval=-1), "reliable_interval"), (dict(history_len=4), "history"),
+])
+def test_cg_rejects_bad_params(lib, kw, msg):
+    p = _params(**kw)
+    res = _lib.WdCgResult()
+    rc = lib.cg_solve(_lat((4, 4, 4, 4)), 0.1, 1, 2, 3, ctypes.byref(p), ctypes.byref(res), 4, 1 << 30, None)
+    assert rc == _lib.WD_ERR_INVALID
+    assert msg in _lib.last_error()
+    assert lib.wd_workspace_bytes(_lat((4, 4, 4, 4)), ctypes.byref(p), 1) == 0
+
+
+def test_cg_rejects_small_workspace(lib):
+    p = _params()
+    need = lib.wd_workspace_bytes(_lat((4, 4, 4, 4)), ctypes.byref(p), 1)
+    assert need > 0
+    res = _lib.WdCgResult()
+    rc = lib.cg_solve(_lat((4, 4, 4, 4)), 0.1, 1, 2, 3, ctypes.byref(p), ctypes.byref(res), 4, need - 1, None)
+    assert rc == _lib.WD_ERR_WORKSPACE
+    rc = lib.cg_solve(_lat((4, 4, 4, 4)), 0.1, 1, 2, 3, ctypes.byref(p), ctypes.byref(res), None, need, None)
+    assert rc == _lib.WD_ERR_WORKSPACE
+
+
+def test_cg_rejects_aliasing(lib):
+    p = _params()
+    rc = lib.cg_solve(_lat((4, 4, 4, 4)), 0.1, 1, 2, 2, ctypes.byref(p), None, 4, 1 << 40, None)
+    assert rc == _lib.WD_ERR_INVALID
+
+
+def test_workspace_sizes_scale(lib):
+    small = lib.wd_workspace_bytes(_lat((4, 4, 4, 4)), ctypes.byref(_params()), 1)
+    big = lib.wd_workspace_bytes(_lat((8, 8, 8, 8)), ctypes.byref(_params()), 1)
+    assert big > 10 * small
+    mixed = lib.wd_workspace_bytes(_lat((8, 8, 8, 8)), ctypes.byref(_params(inner_prec=2)), 1)
+    assert mixed > 0
+
+
+def test_batched_rejects_bad_nrhs(lib):
+    p = _params(inner_prec=1)
+    assert lib.wd_workspace_bytes(_lat((4, 4, 4, 4)), ctypes.byref(p), 0) == 0
+    assert lib.wd_workspace_bytes(_lat((4, 4, 4, 4)), ctypes.byref(p), 17) == 0
+    rc = lib.cg_solve_batched(_lat((4, 4, 4, 4)), 0.1, 1, 0, 2, 3, ctypes.byref(p), None, 4, 1 << 40, None)
+    assert rc == _lib.WD_ERR_INVALID
+
+
+def test_packed_sizes(lib):
+    lat = _lat((4, 4, 4, 4))
+    assert lib.wd_gauge_bytes(lat, 0) == 256 * 4 * 9 * 16
+    assert lib.wd_gauge_bytes(lat, 1) == 256 * 4 * 9 * 8
+    assert lib.wd_gauge_bytes(lat, 2) == 256 * 4 * 9 * 4
+    assert lib.wd_spinor_bytes(lat, 0) == 256 * 192
+    assert lib.wd_spinor_bytes(lat, 3) == 256 * (48 + 4)
+    assert lib.wd_spinor_bytes(lat, 9) == 0
+
+
+def test_product_path_never_touches_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2001_05218_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".hpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"\b(import|from)\s+oracle\b", text), f
+                assert "oracle/" not in text, f
