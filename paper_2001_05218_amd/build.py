@@ -46,9 +46,8 @@ def sources():
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     cmd = [hipcc(), *COMMON, "-c", src, "-o", obj]
-    if src.endswith(".hip"):
-        cmd[1:1] = ["-x", "hip"]
-        cmd += DEVICE
+    cmd[1:1] = ["-x", "hip"]
+    cmd += DEVICE
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

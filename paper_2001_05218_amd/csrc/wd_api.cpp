@@ -4,12 +4,13 @@
 // The paper's host part owns the CG vectors and evaluates the stopping test
 // on the host, invoking the accelerator once per operator application
 // (Sec. 3.1, Sec. 3.1.1). Here every vector and every CG scalar stays in HBM:
-// the reductions finish on the device (last-workgroup-done), alpha and beta
+// the reductions finish on the device (a one-workgroup finalize kernel), alpha and beta
 // never leave it, and the host only enqueues chunks of iterations and polls a
 // copy of the device state between chunks. A device-side status flag turns
 // the kernels of iterations enqueued past convergence into no-ops.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -176,6 +177,14 @@ int validate_params(const wd_cg_params* p) {
   return WD_OK;
 }
 
+// The documented workspace size: for nrhs = 1 it covers both cg_solve and a
+// single-system cg_solve_batched.
+size_t required_bytes(const Geom& g, const wd_cg_params* p, int nrhs) {
+  const size_t batched = batched_workspace_bytes(g, nrhs, p->history_len);
+  if (nrhs == 1) return std::max(layout_cg(nullptr, g, p->inner_prec, p->history_len).bytes, batched);
+  return batched;
+}
+
 }  // namespace
 
 // ====================================================================== ABI
@@ -299,10 +308,8 @@ size_t wd_workspace_bytes(const wd_lattice* lat, const wd_cg_params* params, int
   if (check_lattice(lat)) return 0;
   if (validate_params(params)) return 0;
   if (nrhs < 1) { fail(WD_ERR_INVALID, "nrhs = %d must be >= 1", nrhs); return 0; }
-  const Geom g = make_geom(lat->L);
-  if (nrhs == 1) return layout_cg(nullptr, g, params->inner_prec, params->history_len).bytes;
   if (nrhs > 16) { fail(WD_ERR_INVALID, "nrhs = %d exceeds 16", nrhs); return 0; }
-  return batched_workspace_bytes(g, nrhs, params->history_len);
+  return required_bytes(make_geom(lat->L), params, nrhs);
 }
 
 }  // extern "C"
@@ -548,10 +555,33 @@ extern "C" int cg_solve(const wd_lattice* lat, double mass, const void* U, const
   if (b == x) return fail(WD_ERR_INVALID, "b and x must not alias");
   if (!std::isfinite(mass)) return fail(WD_ERR_INVALID, "mass is not finite");
   const Geom g = make_geom(lat->L);
-  const size_t need = layout_cg(nullptr, g, params->inner_prec, params->history_len).bytes;
+  const size_t need = required_bytes(g, params, 1);
   if (!workspace || ws_bytes < need)
     return fail(WD_ERR_WORKSPACE, "workspace of %zu bytes given, %zu needed", workspace ? ws_bytes : 0, need);
   const hipStream_t s = as_stream(stream);
   if (params->inner_prec == WD_F64) return cg_plain(g, mass, U, b, x, params, result, workspace, s, t0);
   return cg_mixed(g, mass, U, b, x, params, result, workspace, s, t0);
+}
+
+extern "C" int cg_solve_batched(const wd_lattice* lat, double mass, const void* U, int32_t nrhs, const void* B,
+                                void* X, const wd_cg_params* params, wd_cg_result* results, void* workspace,
+                                size_t ws_bytes, void* stream) {
+  if (results && nrhs > 0 && nrhs <= 16) std::memset(results, 0, sizeof(wd_cg_result) * nrhs);
+  int rc = check_lattice(lat);
+  if (rc) return rc;
+  if ((rc = validate_params(params))) return rc;
+  if (nrhs < 1 || nrhs > 16) return fail(WD_ERR_INVALID, "nrhs = %d must be in 1..16", nrhs);
+  if (params->inner_prec != WD_F32)
+    return fail(WD_ERR_INVALID, "batched solves run FP32 inner iterations: inner_prec must be WD_F32");
+  if (!U || !B || !X) return fail(WD_ERR_INVALID, "NULL field pointer");
+  if (B == X) return fail(WD_ERR_INVALID, "B and X must not alias");
+  if (!std::isfinite(mass)) return fail(WD_ERR_INVALID, "mass is not finite");
+  const Geom g = make_geom(lat->L);
+  const size_t need = required_bytes(g, params, nrhs);
+  if (!workspace || ws_bytes < need)
+    return fail(WD_ERR_WORKSPACE, "workspace of %zu bytes given, %zu needed", workspace ? ws_bytes : 0, need);
+  char err[512] = {0};
+  rc = batched_solve(g, mass, U, nrhs, B, X, params, results, workspace, as_stream(stream), err, sizeof(err));
+  if (rc != WD_OK) return fail(rc, "%s", err);
+  return WD_OK;
 }

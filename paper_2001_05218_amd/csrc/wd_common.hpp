@@ -54,17 +54,29 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
   return (uint32_t)(((uint64_t)n * f.m) >> f.k);
 }
 
+// Packed fields number their sites in one of two orders:
+//  * linear: s = x + Lx (y + Ly (z + Lz t)), the canonical order;
+//  * tiled (every extent a multiple of 4): the lattice is cut into 4^4 tiles of
+//    256 sites; s = tile * 256 + local, local = lx + 4 ly + 16 lz + 64 lt, and
+//    tiles are numbered x-fastest. One workgroup of 256 threads then owns one
+//    compact tile, a wavefront one 4x4x4 cube of it, and a 64-site layout block
+//    is exactly that cube.
+// Kernels on the canonical boundary layout always use the linear order.
 struct Geom {
   int L[4];        // Lx, Ly, Lz, Lt
   int V;           // sites
   int Vpad;        // V rounded up to kBlock
   int nblocks;     // Vpad / kBlock
-  int stride[4];   // 1, Lx, Lx*Ly, Lx*Ly*Lz
+  int stride[4];   // linear order: 1, Lx, Lx*Ly, Lx*Ly*Lz
   FastDiv dx, dy, dz;
+  int tiled;       // 1: tiled order (see above)
+  int nt[4];       // tiles per direction (L / 4)
+  int tstride[4];  // tile-index strides: 1, nt0, nt0*nt1, nt0*nt1*nt2
+  FastDiv tdx, tdy, tdz;
 };
 
-inline Geom make_geom(const int L[4]) {
-  Geom g;
+inline Geom make_geom(const int L[4], bool allow_tiled = false) {
+  Geom g{};
   for (int i = 0; i < 4; ++i) g.L[i] = L[i];
   g.V = L[0] * L[1] * L[2] * L[3];
   g.Vpad = (g.V + kBlock - 1) / kBlock * kBlock;
@@ -76,7 +88,67 @@ inline Geom make_geom(const int L[4]) {
   g.dx = make_fastdiv(L[0]);
   g.dy = make_fastdiv(L[1]);
   g.dz = make_fastdiv(L[2]);
+  g.tiled = allow_tiled && (L[0] % 4 == 0) && (L[1] % 4 == 0) && (L[2] % 4 == 0) && (L[3] % 4 == 0);
+  for (int i = 0; i < 4; ++i) g.nt[i] = g.tiled ? L[i] / 4 : 0;
+  if (g.tiled) {
+    g.tstride[0] = 1;
+    g.tstride[1] = g.nt[0];
+    g.tstride[2] = g.nt[0] * g.nt[1];
+    g.tstride[3] = g.nt[0] * g.nt[1] * g.nt[2];
+    g.tdx = make_fastdiv(g.nt[0]);
+    g.tdy = make_fastdiv(g.nt[1]);
+    g.tdz = make_fastdiv(g.nt[2]);
+  }
   return g;
+}
+
+// Tile coordinates of tile index T.
+__device__ __forceinline__ void tile_coords(const Geom& g, uint32_t T, int b[4]) {
+  uint32_t q = fdiv(T, g.tdx);
+  b[0] = (int)(T - q * (uint32_t)g.nt[0]);
+  T = q;
+  q = fdiv(T, g.tdy);
+  b[1] = (int)(T - q * (uint32_t)g.nt[1]);
+  T = q;
+  q = fdiv(T, g.tdz);
+  b[2] = (int)(T - q * (uint32_t)g.nt[2]);
+  b[3] = (int)q;
+}
+
+// Index of the tile next to tile T (coordinates b) in direction mu, step +-1.
+__device__ __forceinline__ int tile_step(const Geom& g, int T, const int b[4], int mu, int step) {
+  if (step > 0) return (b[mu] == g.nt[mu] - 1) ? T - (g.nt[mu] - 1) * g.tstride[mu] : T + g.tstride[mu];
+  return (b[mu] == 0) ? T + (g.nt[mu] - 1) * g.tstride[mu] : T - g.tstride[mu];
+}
+
+// Lattice coordinates (x, y, z, t) of packed site s.
+__device__ __forceinline__ void site_coords(const Geom& g, int s, int c[4]) {
+  if (g.tiled) {
+    int b[4];
+    tile_coords(g, (uint32_t)(s >> 8), b);
+    const int l = s & 255;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) c[mu] = 4 * b[mu] + ((l >> (2 * mu)) & 3);
+  } else {
+    uint32_t r = (uint32_t)s;
+    uint32_t q = fdiv(r, g.dx);
+    c[0] = (int)(r - q * (uint32_t)g.L[0]);
+    r = q;
+    q = fdiv(r, g.dy);
+    c[1] = (int)(r - q * (uint32_t)g.L[1]);
+    r = q;
+    q = fdiv(r, g.dz);
+    c[2] = (int)(r - q * (uint32_t)g.L[2]);
+    c[3] = (int)q;
+  }
+}
+
+// Canonical (linear) index of packed site s.
+__device__ __forceinline__ int canonical_index(const Geom& g, int s) {
+  if (!g.tiled) return s;
+  int c[4];
+  site_coords(g, s, c);
+  return c[0] + g.stride[1] * c[1] + g.stride[2] * c[2] + g.stride[3] * c[3];
 }
 
 // Forward and backward neighbour indices of site s in all four directions.
@@ -86,18 +158,23 @@ struct Nbrs {
 };
 
 __device__ __forceinline__ Nbrs neighbours(const Geom& g, int s) {
-  uint32_t r = (uint32_t)s;
-  uint32_t q = fdiv(r, g.dx);
-  int c[4];
-  c[0] = (int)(r - q * (uint32_t)g.L[0]);
-  r = q;
-  q = fdiv(r, g.dy);
-  c[1] = (int)(r - q * (uint32_t)g.L[1]);
-  r = q;
-  q = fdiv(r, g.dz);
-  c[2] = (int)(r - q * (uint32_t)g.L[2]);
-  c[3] = (int)q;
   Nbrs n;
+  if (g.tiled) {
+    const int T = s >> 8;
+    const int l = s & 255;
+    int b[4];
+    tile_coords(g, (uint32_t)T, b);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      const int lm = (l >> (2 * mu)) & 3;
+      const int ls = 1 << (2 * mu);
+      n.fwd[mu] = (lm < 3) ? s + ls : (tile_step(g, T, b, mu, +1) << 8) + (l - 3 * ls);
+      n.bwd[mu] = (lm > 0) ? s - ls : (tile_step(g, T, b, mu, -1) << 8) + (l + 3 * ls);
+    }
+    return n;
+  }
+  int c[4];
+  site_coords(g, s, c);
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu) {
     const int st = g.stride[mu];

@@ -5,12 +5,13 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "../../include/wilson.h"
 #include "wd_common.hpp"
 
 namespace wd {
 
 // Device-resident solver state. All scalars of the CG recurrences live here,
-// are produced by the last workgroup of a reduction kernel, and are read by
+// are produced by the one-workgroup finalize kernel of a reduction, and are read by
 // the following kernels; the host reads a copy only when it polls.
 struct SolverState {
   double rho;        // <r, r> of the current (inner) residual
@@ -31,13 +32,14 @@ struct SolverState {
   int rel_updates;   // reliable updates performed
   int hist_len;      // capacity of hist
   int pad0;
-  unsigned int ticket;  // last-workgroup-done counter (returns to 0 after every reduction)
+  unsigned int pad2;
   unsigned int pad1;
   double* hist;      // per-iteration relative residual (device, in the workspace)
 };
 
-// When a kernel runs (decided identically by every workgroup from state that
-// only the kernel's own last workgroup may change).
+// When a kernel runs. Decided identically by every workgroup from the state,
+// which only finalize kernels change; a reducing kernel and its finalize
+// kernel carry the same gate and so run or skip together.
 enum Gate : int {
   G_ALWAYS = 0,   // unconditional
   G_ITER = 1,     // a CG iteration: status == 0 and no reliable update pending
@@ -96,6 +98,9 @@ void launch_accumulate(const Geom& g, SpinorBuf x64, SpinorBuf xhat, int gate, S
 void launch_norm2(const Geom& g, SpinorBuf v, int gate, int fin, SolverState* st, double* partials, hipStream_t s);
 // Workspace of the batched persistent solver (wd_batched.hip).
 size_t batched_workspace_bytes(const Geom& g, int nrhs, int hist_len);
+// Batched solve after argument validation; writes a message to err on failure.
+int batched_solve(const Geom& g, double mass, const void* U, int nrhs, const void* B, void* X,
+                  const ::wd_cg_params* p, ::wd_cg_result* res, void* ws, hipStream_t s, char* err, size_t errlen);
 
 // G(a, b) force on canonical complex128 spinors -> canonical complex128 links.
 void launch_force(const Geom& g, const void* a, const void* b, double coeff, int accumulate, void* F, hipStream_t s);

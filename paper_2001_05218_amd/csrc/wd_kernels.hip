@@ -92,29 +92,18 @@ __device__ void finalize(SolverState* st, int fin, double sum) {
   }
 }
 
-// Last-workgroup-done reduction: every workgroup publishes its partial; the
-// workgroup that takes the last ticket sums all partials in index order
-// (deterministic), applies `fin` and re-arms the ticket.
-__device__ void grid_reduce(double v, double* partials, SolverState* st, int fin) {
-  __shared__ int am_last;
+// Per-workgroup partial of a grid-wide sum, written with a plain store; the
+// launcher follows the kernel with k_finalize, which adds the partials in
+// index order (deterministic) and applies `fin` to the solver state. Keeping
+// the cross-workgroup step in its own launch avoids device-scope
+// acquire/release per workgroup, which on a multi-XCD part writes back and
+// invalidates the XCD's L2 and would throw away the stencil's neighbour reuse.
+__device__ __forceinline__ void store_partial(double v, double* partials) {
   const double bs = block_sum(v);
-  if (threadIdx.x == 0) {
-    __hip_atomic_store(&partials[blockIdx.x], bs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned t = __hip_atomic_fetch_add(&st->ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    am_last = (t == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!am_last) return;
-  __atomic_thread_fence(__ATOMIC_ACQUIRE);
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < (int)gridDim.x; i += kBlock)
-    acc += __hip_atomic_load(&partials[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const double total = block_sum(acc);
-  if (threadIdx.x == 0) {
-    finalize(st, fin, total);
-    __hip_atomic_store(&st->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = bs;
 }
+
+constexpr int kFinBlock = 1024;
 
 __device__ __forceinline__ bool gate_open(const SolverState* st, int gate) {
   if (gate == G_ALWAYS || gate == G_FINAL) return true;
@@ -123,6 +112,30 @@ __device__ __forceinline__ bool gate_open(const SolverState* st, int gate) {
   // G_RELIABLE
   return status == 0 && (st->inner_done != 0 || st->iter - st->last_update >= st->interval ||
                          st->rho <= st->delta2 * st->rho_update);
+}
+
+// Sum of n partials in a fixed order, then the state update `fin`. Runs with
+// the same gate as the kernel that wrote the partials (which did not change
+// the state), so both are skipped or run together.
+__global__ __launch_bounds__(kFinBlock) void k_finalize(const double* __restrict__ partials, int n, SolverState* st,
+                                                        int fin, int gate) {
+  if (!gate_open(st, gate)) return;
+  __shared__ double wsum[kFinBlock / 64];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += kFinBlock) v += partials[i];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < kFinBlock / 64; ++i) t += wsum[i];
+    finalize(st, fin, t);
+  }
+}
+
+static void launch_finalize(const Geom& g, double* partials, SolverState* st, int fin, int gate, hipStream_t s) {
+  k_finalize<<<1, kFinBlock, 0, s>>>(partials, g.nblocks, st, fin, gate);
 }
 
 // ------------------------------------------------------- spinor dispatch
@@ -248,7 +261,7 @@ __global__ __launch_bounds__(kBlock) void k_wilson_packed(Geom g, const void* U,
       for (int i = 0; i < 24; ++i) n2 += (double)o[i] * (double)o[i];
     }
   }
-  if (fin != F_NONE) grid_reduce(n2, partials, st, fin);
+  if (fin != F_NONE) store_partial(n2, partials);
 }
 
 // q = D^+ t at site s; r -= alpha q; x += alpha p; reduce ||r||^2 (of the stored r).
@@ -289,7 +302,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(Geom g, const void* U, Spi
       for (int i = 0; i < 24; ++i) n2 += (double)rv[i] * (double)rv[i];
     }
   }
-  grid_reduce(n2, partials, st, F_BETA);
+  store_partial(n2, partials);
 }
 
 // out = low(b - D^+ t) in FP64 arithmetic (t, b and links FP64); reduce the FP64 norm.
@@ -314,7 +327,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(Geom g, const void* U64, Sp
     }
     spinor_of<PO>(out).store(s, o);
   }
-  grid_reduce(n2, partials, st, fin);
+  store_partial(n2, partials);
 }
 
 template <int P>
@@ -363,7 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_norm2(Geom g, SpinorBuf v, int gate,
 #pragma unroll
     for (int i = 0; i < 24; ++i) n2 += (double)a[i] * (double)a[i];
   }
-  grid_reduce(n2, partials, st, fin);
+  store_partial(n2, partials);
 }
 
 // ------------------------------------------------------------------ force
@@ -552,6 +565,7 @@ static void wilson_packed_p(const Geom& g, const void* U, SpinorBuf in, SpinorBu
     k_wilson_packed<P, true><<<grid_of(g), kBlock, 0, s>>>(g, U, in, out, mass + 4.0, gate, fin, st, partials);
   else
     k_wilson_packed<P, false><<<grid_of(g), kBlock, 0, s>>>(g, U, in, out, mass + 4.0, gate, fin, st, partials);
+  if (fin != F_NONE) launch_finalize(g, partials, st, fin, gate, s);
 }
 
 void launch_wilson_packed(const Geom& g, int prec, const void* U, SpinorBuf in, SpinorBuf out, double mass,
@@ -573,6 +587,7 @@ void launch_cg_update(const Geom& g, int prec, const void* U, SpinorBuf t, Spino
     case P_BF16: k_cg_update<P_BF16, P_F32><<<grid_of(g), kBlock, 0, s>>>(g, U, t, r, p, x, diag, st, partials); break;
     default: k_cg_update<P_F16, P_F32><<<grid_of(g), kBlock, 0, s>>>(g, U, t, r, p, x, diag, st, partials); break;
   }
+  launch_finalize(g, partials, st, F_BETA, G_ITER, s);
 }
 
 void launch_residual(const Geom& g, const void* U64, SpinorBuf t64, SpinorBuf b64, SpinorBuf out, double mass,
@@ -584,6 +599,7 @@ void launch_residual(const Geom& g, const void* U64, SpinorBuf t64, SpinorBuf b6
     case P_BF16: k_residual<P_BF16><<<grid_of(g), kBlock, 0, s>>>(g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
     default: k_residual<P_F16><<<grid_of(g), kBlock, 0, s>>>(g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
   }
+  launch_finalize(g, partials, st, fin, gate, s);
 }
 
 void launch_p_update(const Geom& g, SpinorBuf r, SpinorBuf p, SolverState* st, hipStream_t s) {
@@ -607,6 +623,7 @@ void launch_norm2(const Geom& g, SpinorBuf v, int gate, int fin, SolverState* st
     case P_BF16: k_norm2<P_BF16><<<grid_of(g), kBlock, 0, s>>>(g, v, gate, fin, st, partials); break;
     default: k_norm2<P_F16><<<grid_of(g), kBlock, 0, s>>>(g, v, gate, fin, st, partials); break;
   }
+  launch_finalize(g, partials, st, fin, gate, s);
 }
 
 void launch_force(const Geom& g, const void* a, const void* b, double coeff, int accumulate, void* F, hipStream_t s) {

@@ -1,0 +1,112 @@
+"""Batched multi-RHS persistent CG against single-RHS solves, the dense
+inverse and the oracle's operator."""
+import numpy as np
+import pytest
+import torch
+
+import fieldgen
+import oracle
+from gpu_util import log, rel, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+wd = pytest.importorskip("paper_2001_05218_amd")
+
+TOL = 1e-10
+
+
+def _sources(dims, n_gauss, seed):
+    pts = fieldgen.point_sources(dims)
+    gs = fieldgen.gaussian_spinor(dims, seed, nrhs=n_gauss) if n_gauss else np.zeros((0,) + pts.shape[1:])
+    return np.concatenate([pts, gs], axis=0)
+
+
+def test_point_sources_2x2x2x2_dense_inverse():
+    dims, mass = (2, 2, 2, 2), 0.1
+    U = fieldgen.gauge_field(dims, "haar", 301)
+    B = fieldgen.point_sources(dims)
+    X, infos = wd.cg_solve_batched(to_dev(U), to_dev(B), mass, tol=1e-12)
+    Dinv = np.linalg.inv(oracle.dense_D(U, mass, dims))
+    Xn = to_np(X)
+    for k in range(12):
+        # D^+D x = D^+ e_k  =>  x = D^{-1} e_k, column k of the inverse (site 0: index k)
+        assert rel(Xn[k].reshape(-1), Dinv[:, k]) <= 1e-9
+        assert infos[k]["true_rel_res"] <= 1e-12
+
+
+@pytest.mark.parametrize("nrhs", [1, 5, 16])
+def test_each_rhs_matches_single_solve(nrhs):
+    dims, mass = (4, 4, 4, 4), 0.1
+    log(f"batched 4^4 nrhs={nrhs}")
+    U = fieldgen.gauge_field(dims, "haar", 311)
+    B = _sources(dims, max(0, nrhs - 12), 312)[:nrhs] if nrhs >= 12 else fieldgen.gaussian_spinor(dims, 313, nrhs=nrhs)
+    Ut = to_dev(U)
+    X, infos = wd.cg_solve_batched(Ut, to_dev(B), mass, tol=TOL)
+    Xn = to_np(X)
+    for k in range(nrhs):
+        res = oracle.true_relative_residual(U, Xn[k], B[k], mass)
+        assert res <= TOL * (1 + 1e-3), (k, res)
+        assert abs(res - infos[k]["true_rel_res"]) <= 1e-13
+        xs, _ = wd.cg_solve(Ut, to_dev(B[k]), mass, tol=TOL)
+        assert rel(Xn[k], to_np(xs)) <= ((mass + 8) / mass) ** 2 * 2 * TOL
+
+
+def test_normal_mode_and_odd_lattice():
+    dims, mass = (5, 3, 7, 4), 0.05
+    U = fieldgen.gauge_field(dims, "near_identity", 321)
+    B = fieldgen.gaussian_spinor(dims, 322, nrhs=6)
+    X, infos = wd.cg_solve_batched(to_dev(U), to_dev(B), mass, tol=TOL, rhs="normal")
+    Xn = to_np(X)
+    for k in range(6):
+        assert oracle.true_relative_residual(U, Xn[k], B[k], mass, rhs="normal") <= TOL * (1 + 1e-3)
+
+
+def test_complex64_io_and_masks():
+    # point sources converge at different iterations than Gaussian ones: masks
+    dims, mass = (4, 4, 4, 8), 0.05
+    U = fieldgen.gauge_field(dims, "haar", 331)
+    B = _sources(dims, 4, 332).astype(np.complex64)
+    X, infos = wd.cg_solve_batched(to_dev(U), to_dev(B), mass, tol=TOL)
+    assert X.dtype == torch.complex64
+    Xn = to_np(X).astype(np.complex128)
+    its = [i["iterations"] for i in infos]
+    log(f"  iterations per rhs {its}")
+    for k in range(16):
+        assert infos[k]["true_rel_res"] <= TOL
+        # the complex64 output is the FP64 solution rounded: compare with an FP64 solve
+        xr, _ = oracle.cgnr(U, B[k].astype(np.complex128), mass, tol=1e-12)
+        assert rel(Xn[k], xr) <= 2e-6
+
+
+def test_not_converged_reports_partial():
+    dims, mass = (4, 4, 4, 4), 0.1
+    U = fieldgen.gauge_field(dims, "haar", 341)
+    B = fieldgen.gaussian_spinor(dims, 342, nrhs=3)
+    X, infos = wd.cg_solve_batched(to_dev(U), to_dev(B), mass, tol=TOL, max_iter=5, raise_on_nonconvergence=False)
+    Xn = to_np(X)
+    for k in range(3):
+        assert infos[k]["status"] == 1 and infos[k]["iterations"] == 5
+        res = oracle.true_relative_residual(U, Xn[k], B[k], mass)
+        assert abs(res - infos[k]["true_rel_res"]) <= 1e-12
+
+
+def test_config3_24x24x24x48_sixteen_sources():
+    """Full-size batched workload: 12 point sources at the origin + 4 Gaussian,
+    Haar links, m = 0.05; every system's FP64 true residual <= 1e-10, and the
+    oracle's residual at sampled sites of two systems."""
+    dims, mass = (24, 24, 24, 48), 0.05
+    log("batched 24^3x48 x16")
+    U = fieldgen.gauge_field(dims, "haar", 200105248)
+    B = _sources(dims, 4, 200105249)
+    X, infos = wd.cg_solve_batched(to_dev(U), to_dev(B), mass, tol=TOL)
+    its = [i["iterations"] for i in infos]
+    log(f"  iterations {its} seconds {infos[0]['seconds']:.3f}")
+    assert all(i["true_rel_res"] <= TOL for i in infos)
+    Xn = to_np(X)
+    rng = np.random.default_rng(5)
+    sites = [(0, 0, 0, 0), (1, 0, 0, 47)] + [tuple(int(rng.integers(0, L)) for L in dims) for _ in range(6)]
+    for k in (0, 13):
+        lhs = oracle.normal_op_sites(U, Xn[k], mass, sites)
+        rhs = oracle.wilson_D_sites(U, B[k], mass, sites, dagger=True)
+        bn = np.linalg.norm(oracle.wilson_Ddag(U, B[k], mass))
+        assert np.linalg.norm(lhs - rhs) <= TOL * bn

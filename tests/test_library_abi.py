@@ -115,9 +115,9 @@ def test_cg_rejects_aliasing(lib):
 
 
 def test_workspace_sizes_scale(lib):
-    small = lib.wd_workspace_bytes(_lat((4, 4, 4, 4)), ctypes.byref(_params()), 1)
-    big = lib.wd_workspace_bytes(_lat((8, 8, 8, 8)), ctypes.byref(_params()), 1)
-    assert big > 10 * small
+    small = lib.wd_workspace_bytes(_lat((8, 8, 8, 8)), ctypes.byref(_params()), 1)
+    big = lib.wd_workspace_bytes(_lat((16, 16, 16, 16)), ctypes.byref(_params()), 1)
+    assert big > 4 * small
     mixed = lib.wd_workspace_bytes(_lat((8, 8, 8, 8)), ctypes.byref(_params(inner_prec=2)), 1)
     assert mixed > 0
 
