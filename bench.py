@@ -18,6 +18,7 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import subprocess
@@ -42,6 +43,37 @@ TOL = 1e-10
 BYTES_PER_SITE = {"f64": 4 * 9 * 16 + 2 * 192, "f32": 4 * 9 * 8 + 2 * 96, "bf16": 4 * 9 * 4 + 2 * 48,
                   "f16": 4 * 9 * 4 + 2 * 48 + 2 * 4}
 FLOPS_PER_SITE = 1368
+CSRC = os.path.join(ROOT, "paper_2001_05218_amd", "csrc")
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def kernel_source_sha() -> str:
+    """SHA-256 over the HIP sources: a stored counter figure is only valid for
+    the kernels it was measured on."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode())
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel: str, dims) -> dict | None:
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (profiles/traffic_*.txt), or None if absent or measured on other
+    kernel sources."""
+    path = os.path.join(PROFILES, f"traffic_{kernel}_{'x'.join(map(str, dims))}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha") != kernel_source_sha():
+        return None
+    return {"bytes": float(kv["traffic_bytes_per_launch"]), "file": os.path.relpath(path, ROOT)}
 
 
 def log(msg):
@@ -228,12 +260,31 @@ def main():
     torch.cuda.synchronize()
     log(f"dslash: {dsl}")
 
+    # practical ceiling and counter calibration: a plain 512 MiB device copy
+    n = 512 * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    copy_gbs = 2 * n * 4 / (e0.elapsed_time(e1) / 1e3 / 10) / 1e9
+    del src, dst
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, 1 core)")
         cpu = run_cpu_baseline(dims, fp64["iterations"])
 
     kern = dsl[best]
+    # 16-bit storage runs the LDS-staged tile kernel on tileable lattices
+    kname = f"k_wilson_{'tiled' if best in ('bf16', 'f16') else 'packed'}_{best}_dagger"
+    traffic = stored_traffic(kname, dims)
     out = {
         "metric": METRIC,
         "value": per,
@@ -259,8 +310,13 @@ def main():
         "speedup_mixed_vs_fp64": fp64["seconds"] / per,
         "variants": variants,
         "dslash": dsl,
-        "roofline": {"bound": "hbm", "kernel": f"k_wilson_packed<{best}, dagger>", "achieved": kern["GB_per_s"],
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kern["frac_hbm"], "traffic": None},
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": kern["GB_per_s"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kern["frac_hbm"],
+                     "traffic": traffic["bytes"] if traffic else None,
+                     "algorithmic_bytes": kern["bytes_per_launch"],
+                     "traffic_source": traffic["file"] if traffic else None},
+        "copy_ceiling_GB_per_s": copy_gbs,
+        "kernel_source_sha": kernel_source_sha(),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

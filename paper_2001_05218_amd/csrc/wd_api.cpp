@@ -56,6 +56,10 @@ int check_lattice(const wd_lattice* lat) {
   return WD_OK;
 }
 
+// Geometry of the packed (solver-internal) fields: tiled site order when every
+// extent is a multiple of 4.
+Geom packed_geom(const wd_lattice* lat) { return make_geom(lat->L, true); }
+
 bool valid_prec(int p) { return p == WD_F64 || p == WD_F32 || p == WD_BF16 || p == WD_F16; }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -207,7 +211,7 @@ static int apply_common(const wd_lattice* lat, double mass, const void* U, const
   if (!U || !psi || !out) return fail(WD_ERR_INVALID, "NULL field pointer");
   if (psi == out) return fail(WD_ERR_INVALID, "in and out must not alias");
   if (!std::isfinite(mass)) return fail(WD_ERR_INVALID, "mass is not finite");
-  const Geom g = make_geom(lat->L);
+  const Geom g = make_geom(lat->L, false);
   launch_wilson_canonical(g, U, psi, out, mass, dagger, as_stream(stream));
   HIP_TRY(hipGetLastError());
   return WD_OK;
@@ -225,13 +229,13 @@ int wilson_apply_dagger(const wd_lattice* lat, double mass, const void* U, const
 size_t wd_gauge_bytes(const wd_lattice* lat, int32_t prec) {
   if (check_lattice(lat)) return 0;
   if (!valid_prec(prec)) { fail(WD_ERR_INVALID, "prec = %d unknown", prec); return 0; }
-  return gauge_bytes(prec, make_geom(lat->L).Vpad);
+  return gauge_bytes(prec, packed_geom(lat).Vpad);
 }
 
 size_t wd_spinor_bytes(const wd_lattice* lat, int32_t prec) {
   if (check_lattice(lat)) return 0;
   if (!valid_prec(prec)) { fail(WD_ERR_INVALID, "prec = %d unknown", prec); return 0; }
-  const Geom g = make_geom(lat->L);
+  const Geom g = packed_geom(lat);
   return spinor_bytes(prec, g.Vpad) + spinor_scale_bytes(prec, g.Vpad);
 }
 
@@ -249,7 +253,7 @@ int wd_pack_gauge(const wd_lattice* lat, const void* U, int32_t prec, void* out,
   if (rc) return rc;
   if (!valid_prec(prec)) return fail(WD_ERR_INVALID, "prec = %d unknown", prec);
   if (!U || !out) return fail(WD_ERR_INVALID, "NULL field pointer");
-  launch_pack_gauge(make_geom(lat->L), U, prec, out, as_stream(stream));
+  launch_pack_gauge(packed_geom(lat), U, prec, out, as_stream(stream));
   HIP_TRY(hipGetLastError());
   return WD_OK;
 }
@@ -260,7 +264,7 @@ int wd_pack_spinor(const wd_lattice* lat, const void* in, int32_t io_dtype, int3
   if (!valid_prec(prec)) return fail(WD_ERR_INVALID, "prec = %d unknown", prec);
   if (io_dtype != WD_C128 && io_dtype != WD_C64) return fail(WD_ERR_INVALID, "io_dtype = %d unknown", io_dtype);
   if (!in || !out) return fail(WD_ERR_INVALID, "NULL field pointer");
-  const Geom g = make_geom(lat->L);
+  const Geom g = packed_geom(lat);
   launch_pack_spinor(g, in, io_dtype == WD_C64, packed_view(g, prec, out), as_stream(stream));
   HIP_TRY(hipGetLastError());
   return WD_OK;
@@ -273,7 +277,7 @@ int wd_unpack_spinor(const wd_lattice* lat, const void* in, int32_t prec, void* 
   if (!valid_prec(prec)) return fail(WD_ERR_INVALID, "prec = %d unknown", prec);
   if (io_dtype != WD_C128 && io_dtype != WD_C64) return fail(WD_ERR_INVALID, "io_dtype = %d unknown", io_dtype);
   if (!in || !out) return fail(WD_ERR_INVALID, "NULL field pointer");
-  const Geom g = make_geom(lat->L);
+  const Geom g = packed_geom(lat);
   launch_unpack_spinor(g, packed_view(g, prec, in), out, io_dtype == WD_C64, as_stream(stream));
   HIP_TRY(hipGetLastError());
   return WD_OK;
@@ -286,7 +290,7 @@ int wilson_apply_packed(const wd_lattice* lat, double mass, int32_t prec, const 
   if (!valid_prec(prec)) return fail(WD_ERR_INVALID, "prec = %d unknown", prec);
   if (!U_packed || !in_packed || !out_packed) return fail(WD_ERR_INVALID, "NULL field pointer");
   if (in_packed == out_packed) return fail(WD_ERR_INVALID, "in and out must not alias");
-  const Geom g = make_geom(lat->L);
+  const Geom g = packed_geom(lat);
   launch_wilson_packed(g, prec, U_packed, packed_view(g, prec, in_packed), packed_view(g, prec, out_packed), mass,
                        dagger ? 1 : 0, G_ALWAYS, F_NONE, nullptr, nullptr, as_stream(stream));
   HIP_TRY(hipGetLastError());
@@ -299,7 +303,7 @@ int wilson_force(const wd_lattice* lat, const void* a, const void* b, double coe
   if (rc) return rc;
   if (!a || !b || !F) return fail(WD_ERR_INVALID, "NULL field pointer");
   if (!std::isfinite(coeff)) return fail(WD_ERR_INVALID, "coeff is not finite");
-  launch_force(make_geom(lat->L), a, b, coeff, accumulate ? 1 : 0, F, as_stream(stream));
+  launch_force(make_geom(lat->L, false), a, b, coeff, accumulate ? 1 : 0, F, as_stream(stream));
   HIP_TRY(hipGetLastError());
   return WD_OK;
 }
@@ -309,7 +313,7 @@ size_t wd_workspace_bytes(const wd_lattice* lat, const wd_cg_params* params, int
   if (validate_params(params)) return 0;
   if (nrhs < 1) { fail(WD_ERR_INVALID, "nrhs = %d must be >= 1", nrhs); return 0; }
   if (nrhs > 16) { fail(WD_ERR_INVALID, "nrhs = %d exceeds 16", nrhs); return 0; }
-  return required_bytes(make_geom(lat->L), params, nrhs);
+  return required_bytes(packed_geom(lat), params, nrhs);
 }
 
 }  // extern "C"
@@ -554,7 +558,7 @@ extern "C" int cg_solve(const wd_lattice* lat, double mass, const void* U, const
   if (!U || !b || !x) return fail(WD_ERR_INVALID, "NULL field pointer");
   if (b == x) return fail(WD_ERR_INVALID, "b and x must not alias");
   if (!std::isfinite(mass)) return fail(WD_ERR_INVALID, "mass is not finite");
-  const Geom g = make_geom(lat->L);
+  const Geom g = packed_geom(lat);
   const size_t need = required_bytes(g, params, 1);
   if (!workspace || ws_bytes < need)
     return fail(WD_ERR_WORKSPACE, "workspace of %zu bytes given, %zu needed", workspace ? ws_bytes : 0, need);
@@ -576,7 +580,7 @@ extern "C" int cg_solve_batched(const wd_lattice* lat, double mass, const void* 
   if (!U || !B || !X) return fail(WD_ERR_INVALID, "NULL field pointer");
   if (B == X) return fail(WD_ERR_INVALID, "B and X must not alias");
   if (!std::isfinite(mass)) return fail(WD_ERR_INVALID, "mass is not finite");
-  const Geom g = make_geom(lat->L);
+  const Geom g = packed_geom(lat);
   const size_t need = required_bytes(g, params, nrhs);
   if (!workspace || ws_bytes < need)
     return fail(WD_ERR_WORKSPACE, "workspace of %zu bytes given, %zu needed", workspace ? ws_bytes : 0, need);

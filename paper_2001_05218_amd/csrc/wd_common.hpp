@@ -196,18 +196,21 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 
 // ----------------------------------------------------------- conversions
 
-__device__ __forceinline__ uint32_t f2bf_bits(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return ((u >> 16) | 0x40u) & 0xffffu;
-  u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest even
-  return u >> 16;
+// Two floats -> two 16-bit values in one word (lo in bits 0..15), rounded to
+// nearest even by gfx950's v_cvt_pk_bf16_f32 / v_cvt_pk_f16_f32.
+typedef __bf16 wd_bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 wd_f16x2 __attribute__((ext_vector_type(2)));
+typedef float wd_f32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+  const wd_f32x2 v = {lo, hi};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, wd_bf16x2));
+}
+__device__ __forceinline__ uint32_t pack_f16x2(float lo, float hi) {
+  const wd_f32x2 v = {lo, hi};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, wd_f16x2));
 }
 __device__ __forceinline__ float bf_bits2f(uint32_t b) { return __uint_as_float(b << 16); }
-
-__device__ __forceinline__ uint32_t f2h_bits(float f) {
-  _Float16 h = (_Float16)f;          // v_cvt_f16_f32, round to nearest even
-  return (uint32_t)__builtin_bit_cast(uint16_t, h);
-}
 __device__ __forceinline__ float h_bits2f(uint32_t b) {
   return (float)__builtin_bit_cast(_Float16, (uint16_t)(b & 0xffffu));
 }
@@ -267,11 +270,10 @@ template <> struct PackedSpinor<P_BF16> {
   using Real = float;
   uint4* data;
   float* scale;
-  __device__ __forceinline__ void load(int s, Real v[24]) const {
+  static __device__ __forceinline__ void unpack(const uint4 d[3], float, Real v[24]) {
 #pragma unroll
     for (int w = 0; w < 3; ++w) {
-      uint4 d = data[word_index(s, 3, w)];
-      uint32_t u[4] = {d.x, d.y, d.z, d.w};
+      const uint32_t u[4] = {d[w].x, d[w].y, d[w].z, d[w].w};
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         v[8 * w + 2 * k] = bf_bits2f(u[k] & 0xffffu);
@@ -279,12 +281,19 @@ template <> struct PackedSpinor<P_BF16> {
       }
     }
   }
+  __device__ __forceinline__ float load_scale(int) const { return 1.0f; }
+  __device__ __forceinline__ void load(int s, Real v[24]) const {
+    uint4 d[3];
+#pragma unroll
+    for (int w = 0; w < 3; ++w) d[w] = data[word_index(s, 3, w)];
+    unpack(d, 1.0f, v);
+  }
   __device__ __forceinline__ void store(int s, const Real v[24]) const {
 #pragma unroll
     for (int w = 0; w < 3; ++w) {
       uint32_t u[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) u[k] = f2bf_bits(v[8 * w + 2 * k]) | (f2bf_bits(v[8 * w + 2 * k + 1]) << 16);
+      for (int k = 0; k < 4; ++k) u[k] = pack_bf16x2(v[8 * w + 2 * k], v[8 * w + 2 * k + 1]);
       data[word_index(s, 3, w)] = make_uint4(u[0], u[1], u[2], u[3]);
     }
   }
@@ -294,18 +303,23 @@ template <> struct PackedSpinor<P_F16> {
   using Real = float;
   uint4* data;
   float* scale;   // per-site magnitude: stored value = v / scale, |stored| <= 1
-  __device__ __forceinline__ void load(int s, Real v[24]) const {
-    const float sc = scale[s];
+  static __device__ __forceinline__ void unpack(const uint4 d[3], float sc, Real v[24]) {
 #pragma unroll
     for (int w = 0; w < 3; ++w) {
-      uint4 d = data[word_index(s, 3, w)];
-      uint32_t u[4] = {d.x, d.y, d.z, d.w};
+      const uint32_t u[4] = {d[w].x, d[w].y, d[w].z, d[w].w};
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         v[8 * w + 2 * k] = h_bits2f(u[k]) * sc;
         v[8 * w + 2 * k + 1] = h_bits2f(u[k] >> 16) * sc;
       }
     }
+  }
+  __device__ __forceinline__ float load_scale(int s) const { return scale[s]; }
+  __device__ __forceinline__ void load(int s, Real v[24]) const {
+    uint4 d[3];
+#pragma unroll
+    for (int w = 0; w < 3; ++w) d[w] = data[word_index(s, 3, w)];
+    unpack(d, scale[s], v);
   }
   __device__ __forceinline__ void store(int s, const Real v[24]) const {
     float m = 0.f;
@@ -318,7 +332,7 @@ template <> struct PackedSpinor<P_F16> {
       uint32_t u[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k)
-        u[k] = f2h_bits(v[8 * w + 2 * k] * inv) | (f2h_bits(v[8 * w + 2 * k + 1] * inv) << 16);
+        u[k] = pack_f16x2(v[8 * w + 2 * k] * inv, v[8 * w + 2 * k + 1] * inv);
       data[word_index(s, 3, w)] = make_uint4(u[0], u[1], u[2], u[3]);
     }
   }
@@ -384,6 +398,17 @@ template <> struct PackedGauge<P_F32> {
     }
   }
 };
+
+// One complex link entry from its 16-bit pair (re low, im high).
+template <int P> __device__ __forceinline__ void unpack_link16(uint32_t d, float& re, float& im) {
+  if constexpr (P == P_BF16) {
+    re = bf_bits2f(d & 0xffffu);
+    im = bf_bits2f(d >> 16);
+  } else {
+    re = h_bits2f(d);
+    im = h_bits2f(d >> 16);
+  }
+}
 
 template <> struct PackedGauge<P_BF16> {
   using Real = float;

@@ -5,6 +5,7 @@
 
 #include "wd_dslash.hpp"
 #include "wd_internal.hpp"
+#include "wd_tiled.hpp"
 
 namespace wd {
 
@@ -158,17 +159,18 @@ template <int P>
 __global__ __launch_bounds__(kBlock) void k_pack_gauge(Geom g, const double2* __restrict__ U, void* out) {
   const int s = blockIdx.x * kBlock + threadIdx.x;
   if (s >= g.V) return;
+  const int c = canonical_index(g, s);
   for (int mu = 0; mu < 4; ++mu) {
-    const double2* src = U + ((size_t)mu * g.V + s) * 9;
+    const double2* src = U + ((size_t)mu * g.V + c) * 9;
     for (int e = 0; e < 9; ++e) {
       const double2 d = src[e];
       const size_t w = word_index(s, 36, mu * 9 + e);
       if constexpr (P == P_F64) reinterpret_cast<double2*>(out)[w] = d;
       else if constexpr (P == P_F32) reinterpret_cast<float2*>(out)[w] = make_float2((float)d.x, (float)d.y);
       else if constexpr (P == P_BF16)
-        reinterpret_cast<uint32_t*>(out)[w] = f2bf_bits((float)d.x) | (f2bf_bits((float)d.y) << 16);
+        reinterpret_cast<uint32_t*>(out)[w] = pack_bf16x2((float)d.x, (float)d.y);
       else
-        reinterpret_cast<uint32_t*>(out)[w] = f2h_bits((float)d.x) | (f2h_bits((float)d.y) << 16);
+        reinterpret_cast<uint32_t*>(out)[w] = pack_f16x2((float)d.x, (float)d.y);
     }
   }
 }
@@ -179,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_spinor(Geom g, const IO* __rest
   if (s >= g.V) return;
   using R = typename PackedSpinor<P>::Real;
   R v[24];
-  const IO* p = in + (size_t)s * 12;
+  const IO* p = in + (size_t)canonical_index(g, s) * 12;
 #pragma unroll
   for (int i = 0; i < 12; ++i) {
     v[2 * i] = (R)p[i].x;
@@ -195,7 +197,7 @@ __global__ __launch_bounds__(kBlock) void k_unpack_spinor(Geom g, SpinorBuf in, 
   using R = typename PackedSpinor<P>::Real;
   R v[24];
   spinor_of<P>(in).load(s, v);
-  IO* p = out + (size_t)s * 12;
+  IO* p = out + (size_t)canonical_index(g, s) * 12;
 #pragma unroll
   for (int i = 0; i < 12; ++i) {
     IO d;
@@ -264,9 +266,69 @@ __global__ __launch_bounds__(kBlock) void k_wilson_packed(Geom g, const void* U,
   if (fin != F_NONE) store_partial(n2, partials);
 }
 
+// LDS-staged stencil (16-bit storage, tiled order): one workgroup per 4^4 tile.
+// At most 128 VGPRs (4 waves per SIMD): without the bound the BF16
+// instantiation hoists unpacking into 256+ registers and runs one wave per SIMD.
+#define WD_TILED_OCCUPANCY __attribute__((amdgpu_waves_per_eu(4, 8)))
+
+template <int P, bool DAG>
+__global__ __launch_bounds__(kBlock) WD_TILED_OCCUPANCY void k_wilson_tiled(Geom g, const void* U, SpinorBuf in, SpinorBuf out,
+                                                         double diag, int gate, int fin, SolverState* st,
+                                                         double* partials) {
+  if (!gate_open(st, gate)) return;
+  __shared__ TileLds<P> lds;
+  const int T = xcd_tile(blockIdx.x, gridDim.x);
+  uint32_t lk[8][9];
+  tile_stage<P>(g, T, U, in, lds, lk);
+  __syncthreads();
+  float o[24];
+  tile_wilson<P, DAG>(lds, lk, (float)diag, o);
+  spinor_of<P>(out).store(T * kTileSites + threadIdx.x, o);
+  if (fin != F_NONE) {
+    double n2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 24; ++i) n2 += (double)o[i] * (double)o[i];
+    store_partial(n2, partials);
+  }
+}
+
+// CG update with the LDS-staged D^+ (16-bit storage, tiled order).
+template <int P>
+__global__ __launch_bounds__(kBlock) WD_TILED_OCCUPANCY void k_cg_update_tiled(Geom g, const void* U, SpinorBuf t, SpinorBuf r,
+                                                            SpinorBuf p, SpinorBuf x, double diag, SolverState* st,
+                                                            double* partials) {
+  if (!gate_open(st, G_ITER)) return;
+  __shared__ TileLds<P> lds;
+  const int T = xcd_tile(blockIdx.x, gridDim.x);
+  uint32_t lk[8][9];
+  tile_stage<P>(g, T, U, t, lds, lk);
+  __syncthreads();
+  float q[24];
+  tile_wilson<P, true>(lds, lk, (float)diag, q);
+  const int s = T * kTileSites + threadIdx.x;
+  const float a = (float)st->alpha;
+  float rv[24], pv[24], xv[24];
+  const auto rs = spinor_of<P>(r);
+  rs.load(s, rv);
+  spinor_of<P>(p).load(s, pv);
+  spinor_of<P_F32>(x).load(s, xv);
+#pragma unroll
+  for (int i = 0; i < 24; ++i) {
+    rv[i] = fmaf(-a, q[i], rv[i]);
+    xv[i] = fmaf(a, pv[i], xv[i]);
+  }
+  rs.store(s, rv);
+  spinor_of<P_F32>(x).store(s, xv);
+  rs.load(s, rv);   // the norm of what the next iteration reads
+  double n2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < 24; ++i) n2 += (double)rv[i] * (double)rv[i];
+  store_partial(n2, partials);
+}
+
 // q = D^+ t at site s; r -= alpha q; x += alpha p; reduce ||r||^2 (of the stored r).
 template <int P, int PX>
-__global__ __launch_bounds__(kBlock) void k_cg_update(Geom g, const void* U, SpinorBuf t, SpinorBuf r, SpinorBuf p,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_cg_update(Geom g, const void* U, SpinorBuf t, SpinorBuf r, SpinorBuf p,
                                                       SpinorBuf x, double diag, SolverState* st, double* partials) {
   if (!gate_open(st, G_ITER)) return;
   using R = typename PackedSpinor<P>::Real;
@@ -278,6 +340,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(Geom g, const void* U, Spi
     const Nbrs nb = neighbours(g, s);
     R q[24];
     wilson_site<true>(gauge_of<P>(U), spinor_of<P>(t), s, nb, (R)diag, q);
+    // the epilogue's loads are not hoisted into the stencil (register pressure)
+    __builtin_amdgcn_sched_barrier(0);
     R rv[24], pv[24];
     RX xv[24];
     const auto rs = spinor_of<P>(r);
@@ -561,6 +625,16 @@ void launch_wilson_canonical(const Geom& g, const void* U, const void* in, void*
 template <int P>
 static void wilson_packed_p(const Geom& g, const void* U, SpinorBuf in, SpinorBuf out, double mass, int dagger,
                             int gate, int fin, SolverState* st, double* partials, hipStream_t s) {
+  if constexpr (P == P_BF16 || P == P_F16) {
+    if (g.tiled) {
+      if (dagger)
+        k_wilson_tiled<P, true><<<grid_of(g), kBlock, 0, s>>>(g, U, in, out, mass + 4.0, gate, fin, st, partials);
+      else
+        k_wilson_tiled<P, false><<<grid_of(g), kBlock, 0, s>>>(g, U, in, out, mass + 4.0, gate, fin, st, partials);
+      if (fin != F_NONE) launch_finalize(g, partials, st, fin, gate, s);
+      return;
+    }
+  }
   if (dagger)
     k_wilson_packed<P, true><<<grid_of(g), kBlock, 0, s>>>(g, U, in, out, mass + 4.0, gate, fin, st, partials);
   else
@@ -584,8 +658,14 @@ void launch_cg_update(const Geom& g, int prec, const void* U, SpinorBuf t, Spino
   switch (prec) {
     case P_F64: k_cg_update<P_F64, P_F64><<<grid_of(g), kBlock, 0, s>>>(g, U, t, r, p, x, diag, st, partials); break;
     case P_F32: k_cg_update<P_F32, P_F32><<<grid_of(g), kBlock, 0, s>>>(g, U, t, r, p, x, diag, st, partials); break;
-    case P_BF16: k_cg_update<P_BF16, P_F32><<<grid_of(g), kBlock, 0, s>>>(g, U, t, r, p, x, diag, st, partials); break;
-    default: k_cg_update<P_F16, P_F32><<<grid_of(g), kBlock, 0, s>>>(g, U, t, r, p, x, diag, st, partials); break;
+    case P_BF16:
+      if (g.tiled) k_cg_update_tiled<P_BF16><<<grid_of(g), kBlock, 0, s>>>(g, U, t, r, p, x, diag, st, partials);
+      else k_cg_update<P_BF16, P_F32><<<grid_of(g), kBlock, 0, s>>>(g, U, t, r, p, x, diag, st, partials);
+      break;
+    default:
+      if (g.tiled) k_cg_update_tiled<P_F16><<<grid_of(g), kBlock, 0, s>>>(g, U, t, r, p, x, diag, st, partials);
+      else k_cg_update<P_F16, P_F32><<<grid_of(g), kBlock, 0, s>>>(g, U, t, r, p, x, diag, st, partials);
+      break;
   }
   launch_finalize(g, partials, st, F_BETA, G_ITER, s);
 }

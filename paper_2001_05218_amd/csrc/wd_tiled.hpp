@@ -1,0 +1,150 @@
+// LDS-staged Wilson stencil for 16-bit fields in the tiled site order.
+//
+// The paper keeps the inputs of neighbouring stencils on chip in cyclic
+// buffers so that each datum crosses the memory interface once (Sec. 2).
+// On gfx950 the caches cannot be trusted with that reuse: at full bandwidth
+// an XCD's 4 MB L2 turns over in a few microseconds, less than the time a
+// wavefront spends walking its eight hops, and measured L2 hit rates of the
+// cache-only stencil are ~10 %. Here a workgroup owns one 4^4 tile and
+//   1. issues, all at once, the loads of its 256 spinors plus the 8 halo
+//      faces (64 sites each, read from the neighbouring tiles) into LDS, and
+//      of its sites' 8 links (4 own, 4 backward) into registers;
+//   2. after one barrier evaluates all 8 hops from LDS and registers.
+// A workgroup's loads are thus in flight together; the faces it reads are the
+// interiors of tiles that neighbouring workgroups of the same XCD stage at the
+// same moment, so they are served by that XCD's L2.
+//
+// Slot map of the LDS staging area: 0..255 interior (slot = local index),
+// 256 + (2 mu) * 64 + f: the +mu face, 256 + (2 mu + 1) * 64 + f: the -mu face,
+// f = the local index with its 2 bits of coordinate mu removed.
+#pragma once
+
+#include "wd_dslash.hpp"
+
+namespace wd {
+
+constexpr int kTileSites = 256;
+constexpr int kTileSlots = 768;
+
+__device__ __forceinline__ int face_pos(int l, int mu) {
+  const int lo = l & ((1 << (2 * mu)) - 1);
+  const int hi = l >> (2 * mu + 2);
+  return lo | (hi << (2 * mu));
+}
+__device__ __forceinline__ int face_insert(int f, int mu, int v) {
+  const int lo = f & ((1 << (2 * mu)) - 1);
+  const int hi = f >> (2 * mu);
+  return lo | (v << (2 * mu)) | (hi << (2 * mu + 2));
+}
+
+template <int P>
+struct TileLds {
+  uint4 w[3][kTileSlots];
+  float scale[kTileSlots];
+};
+
+// Stage the tile's spinors and halo faces; prefetch the 8 links of site s.
+template <int P>
+__device__ __forceinline__ void tile_stage(const Geom& g, int T, const void* Uv, const SpinorBuf& in, TileLds<P>& lds,
+                                           uint32_t lk[8][9]) {
+  const int l = threadIdx.x;
+  const int s = T * kTileSites + l;
+  const uint32_t* U = static_cast<const uint32_t*>(Uv);
+  const uint4* src = static_cast<const uint4*>(in.data);
+  const Nbrs nb = neighbours(g, s);
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+    for (int e = 0; e < 9; ++e) lk[mu][e] = U[word_index(s, 36, mu * 9 + e)];
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+    for (int e = 0; e < 9; ++e) lk[4 + mu][e] = U[word_index(nb.bwd[mu], 36, mu * 9 + e)];
+#pragma unroll
+  for (int w = 0; w < 3; ++w) lds.w[w][l] = src[word_index(s, 3, w)];
+  if constexpr (P == P_F16) lds.scale[l] = in.scale[s];
+  // halo: wavefront mu stages the two mu faces
+  const int mu = l >> 6;
+  const int f = l & 63;
+  int b[4];
+  tile_coords(g, (uint32_t)T, b);
+  const int sp = tile_step(g, T, b, mu, +1) * kTileSites + face_insert(f, mu, 0);
+  const int sm = tile_step(g, T, b, mu, -1) * kTileSites + face_insert(f, mu, 3);
+  const int slot_p = kTileSites + (2 * mu) * 64 + f;
+  const int slot_m = kTileSites + (2 * mu + 1) * 64 + f;
+#pragma unroll
+  for (int w = 0; w < 3; ++w) {
+    lds.w[w][slot_p] = src[word_index(sp, 3, w)];
+    lds.w[w][slot_m] = src[word_index(sm, 3, w)];
+  }
+  if constexpr (P == P_F16) {
+    lds.scale[slot_p] = in.scale[sp];
+    lds.scale[slot_m] = in.scale[sm];
+  }
+}
+
+template <int P>
+__device__ __forceinline__ void tile_spinor(const TileLds<P>& lds, int slot, float v[24]) {
+  uint4 d[3];
+#pragma unroll
+  for (int w = 0; w < 3; ++w) d[w] = lds.w[w][slot];
+  PackedSpinor<P>::unpack(d, P == P_F16 ? lds.scale[slot] : 1.0f, v);
+}
+
+// Unpack a prefetched link at its point of use. The empty asm makes each raw
+// word opaque here, so the compiler cannot unpack all eight links right after
+// their loads (which would keep 144 floats live instead of 72 raw words).
+template <int P>
+__device__ __forceinline__ void link_from(const uint32_t raw[9], float u[18]) {
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    uint32_t r = raw[e];
+    asm volatile("" : "+v"(r));
+    unpack_link16<P>(r, u[2 * e], u[2 * e + 1]);
+  }
+}
+
+template <int P, int MU, bool DAG>
+__device__ __forceinline__ void tile_hop(const TileLds<P>& lds, const uint32_t lk[8][9], int l, float acc[24]) {
+  constexpr int SF = DAG ? +1 : -1;
+  constexpr int SB = -SF;
+  constexpr int ls = 1 << (2 * MU);
+  const int lm = (l >> (2 * MU)) & 3;
+  const int fp = face_pos(l, MU);
+  const int slot_f = (lm < 3) ? l + ls : kTileSites + (2 * MU) * 64 + fp;
+  const int slot_b = (lm > 0) ? l - ls : kTileSites + (2 * MU + 1) * 64 + fp;
+  float psi[24], h[12], w[12], u[18];
+  tile_spinor<P>(lds, slot_f, psi);
+  link_from<P>(lk[MU], u);
+  project<MU, SF>(psi, h);
+  su3_mul_half<false>(u, h, w);
+  reconstruct_add<MU, SF>(acc, w);
+  tile_spinor<P>(lds, slot_b, psi);
+  link_from<P>(lk[4 + MU], u);
+  project<MU, SB>(psi, h);
+  su3_mul_half<true>(u, h, w);
+  reconstruct_add<MU, SB>(acc, w);
+  // keep the scheduler from hoisting the next hop's LDS reads and unpacking
+  // above this one (that multiplies the live registers for 16-bit data)
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// out = D in (or D^+ in) at this thread's site of tile T, after tile_stage and a barrier.
+template <int P, bool DAG>
+__device__ __forceinline__ void tile_wilson(const TileLds<P>& lds, const uint32_t lk[8][9], float diag,
+                                            float out[24]) {
+  const int l = threadIdx.x;
+  float acc[24];
+#pragma unroll
+  for (int i = 0; i < 24; ++i) acc[i] = 0.f;
+  tile_hop<P, 0, DAG>(lds, lk, l, acc);
+  tile_hop<P, 1, DAG>(lds, lk, l, acc);
+  tile_hop<P, 2, DAG>(lds, lk, l, acc);
+  tile_hop<P, 3, DAG>(lds, lk, l, acc);
+  float c[24];
+  tile_spinor<P>(lds, l, c);
+#pragma unroll
+  for (int i = 0; i < 24; ++i) out[i] = fmaf(diag, c[i], -0.5f * acc[i]);
+}
+
+}  // namespace wd
