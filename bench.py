@@ -43,6 +43,31 @@ TOL = 1e-10
 BYTES_PER_SITE = {"f64": 4 * 9 * 16 + 2 * 192, "f32": 4 * 9 * 8 + 2 * 96, "bf16": 4 * 9 * 4 + 2 * 48,
                   "f16": 4 * 9 * 4 + 2 * 48 + 2 * 4}
 FLOPS_PER_SITE = 1368
+# algorithmic bytes per site of the inner loop's three kernels, by storage:
+#   D p       : 4 links + p in + t out
+#   update    : 4 links + t in (D^+ t) + r in/out + p in + x(hat) in/out (FP32, FP64 for plain CG)
+#   p update  : r in + p in + p out
+SPINOR_B = {"f64": 192, "f32": 96, "bf16": 48, "f16": 52}
+LINKS_B = {"f64": 576, "f32": 288, "bf16": 144, "f16": 144}
+
+
+def loop_kernel_bytes(prec, two_row_links=False):
+    """Bytes per site each inner-loop kernel moves; two-row links store 6 of the
+    9 entries of each link (row 2 is rebuilt from unitarity)."""
+    sp, lk = SPINOR_B[prec], LINKS_B[prec]
+    if two_row_links:
+        lk = lk * 2 // 3
+    xb = 2 * (192 if prec == "f64" else 96)
+    return {"D": lk + 2 * sp, "update": lk + sp + 2 * sp + sp + xb, "p_update": 3 * sp}
+
+
+KERNEL_NAMES = {  # kernel that runs each loop step for a storage precision (tiled lattice)
+    "D": {"f64": "k_wilson_packed_f64", "f32": "k_wilson_packed_f32", "bf16": "k_wilson_tiled_bf16",
+          "f16": "k_wilson_tiled_f16"},
+    "update": {"f64": "k_cg_update_f64", "f32": "k_cg_update_f32", "bf16": "k_cg_update_tiled_bf16",
+               "f16": "k_cg_update_tiled_f16"},
+    "p_update": {p: f"k_p_update_{p}" for p in ("f64", "f32", "bf16", "f16")},
+}
 CSRC = os.path.join(ROOT, "paper_2001_05218_amd", "csrc")
 PROFILES = os.path.join(ROOT, "profiles")
 
@@ -210,13 +235,24 @@ def main():
     infos = []
     for _ in range(args.steps):
         x, info = wd.cg_solve(Ut, bt, MASS, tol=TOL, max_iter=20000, inner=best, reliable_interval=50,
-                              workspace=ws[best])
+                              workspace=ws[best], profile=True)
         infos.append(info)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     per = elapsed / args.steps
     assert all(i["true_rel_res"] <= TOL for i in infos), infos
     log(f"mixed {best}: {per:.4f} s per solve")
+
+    # the other two-precision scheme, for comparison (outside the timed region)
+    torch.cuda.synchronize()
+    t_ir = time.perf_counter()
+    _, iref = wd.cg_solve(Ut, bt, MASS, tol=TOL, max_iter=20000, inner=best, workspace=ws[best],
+                          scheme="refinement", inner_tol=0.1)
+    torch.cuda.synchronize()
+    tref = time.perf_counter() - t_ir
+    refinement = {"seconds": tref, "iterations": iref["iterations"], "cycles": iref["reliable_updates"],
+                  "true_rel_res": iref["true_rel_res"], "inner_tol": 0.1}
+    log(f"refinement {best}: {refinement}")
 
     # error of the mixed solution against the FP64 solution and a sampled
     # oracle residual (the oracle evaluates D^+D x site by site)
@@ -281,10 +317,21 @@ def main():
         log("cpu baseline (oracle, 1 core)")
         cpu = run_cpu_baseline(dims, fp64["iterations"])
 
-    kern = dsl[best]
-    # 16-bit storage runs the LDS-staged tile kernel on tileable lattices
-    kname = f"k_wilson_{'tiled' if best in ('bf16', 'f16') else 'packed'}_{best}_dagger"
-    traffic = stored_traffic(kname, dims)
+    # the inner loop's kernels, timed with HIP events on the solver's stream
+    # during the timed solves (first 64 iterations of each)
+    rows2 = bool(infos[-1]["two_row_links"])
+    kb = loop_kernel_bytes(best, rows2)
+    loop = {}
+    for j, kind in enumerate(("D", "update", "p_update")):
+        secs = float(np.mean([i["kernel_seconds"][j] for i in infos]))
+        gbs = kb[kind] * V / secs / 1e9 if secs > 0 else 0.0
+        name = KERNEL_NAMES[kind][best] + ("_rows2" if rows2 and kind != "p_update" else "")
+        loop[kind] = {"kernel": name, "avg_us": secs * 1e6, "bytes_per_site": kb[kind],
+                      "GB_per_s": gbs, "frac_hbm": gbs / HBM_PEAK_GBS,
+                      "ms_per_solve": secs * 1e3 * infos[-1]["iterations"]}
+    dom = max(loop, key=lambda k: loop[k]["ms_per_solve"])
+    kern = loop[dom]
+    traffic = stored_traffic(kern["kernel"], dims)
     out = {
         "metric": METRIC,
         "value": per,
@@ -304,17 +351,21 @@ def main():
                    "lattice_xyzt": list(dims), "mass": MASS, "tol": TOL, "inner_storage": best,
                    "reliable_interval": 50},
         "mixed_cg": {"seconds": per, "iterations": infos[-1]["iterations"],
+                     "two_row_links": bool(infos[-1]["two_row_links"]),
                      "reliable_updates": infos[-1]["reliable_updates"], "true_rel_res": infos[-1]["true_rel_res"],
                      "rel_diff_vs_fp64_solution": diff, "sampled_oracle_residual": sampled},
         "fp64_cg": fp64,
+        "refinement_cg": refinement,
         "speedup_mixed_vs_fp64": fp64["seconds"] / per,
         "variants": variants,
         "dslash": dsl,
-        "roofline": {"bound": "hbm", "kernel": kname, "achieved": kern["GB_per_s"],
+        "roofline": {"bound": "hbm", "kernel": kern["kernel"], "achieved": kern["GB_per_s"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kern["frac_hbm"],
                      "traffic": traffic["bytes"] if traffic else None,
-                     "algorithmic_bytes": kern["bytes_per_launch"],
+                     "algorithmic_bytes": kern["bytes_per_site"] * V,
+                     "avg_launch_us": kern["avg_us"],
                      "traffic_source": traffic["file"] if traffic else None},
+        "loop_kernels": loop,
         "copy_ceiling_GB_per_s": copy_gbs,
         "kernel_source_sha": kernel_source_sha(),
         "cpu_baseline": cpu,

@@ -53,11 +53,23 @@ typedef struct {
 
 /* storage / arithmetic precision of the solver's inner iterations */
 enum { WD_F64 = 0, WD_F32 = 1, WD_BF16 = 2, WD_F16 = 3 };
+/* OR-ed into the precision of a packed GAUGE field (wd_gauge_bytes, wd_pack_gauge,
+ * wilson_apply_packed): store rows 0 and 1 of each link only and rebuild row 2
+ * as conj(row0 x row1). Valid for SU(3) links (the caller guarantees it),
+ * WD_BF16 / WD_F16, and lattices whose extents are all multiples of 4. */
+enum { WD_TWO_ROW_LINKS = 0x100 };
 /* which system cg_solve solves */
 enum { WD_RHS_SOURCE = 0, /* D^+ D x = D^+ b  (x = D^-1 b) */
        WD_RHS_NORMAL = 1  /* D^+ D x = b                   */ };
 /* element type of b and x at the boundary */
 enum { WD_C128 = 0, WD_C64 = 1 };
+/* two-precision scheme of a mixed solve (inner_prec != WD_F64) */
+enum { WD_RELIABLE_UPDATE = 0,      /* one Krylov space; the FP64 residual replaces the
+                                       low-precision one every reliable_interval iterations
+                                       and after each inner_tol reduction (default) */
+       WD_ITERATIVE_REFINEMENT = 1  /* defect correction: x += e with D^+D e = r solved in low
+                                       precision to inner_tol from e = 0 (a new Krylov space
+                                       per cycle), r recomputed in FP64 after each cycle */ };
 
 enum {
   WD_OK = 0,
@@ -81,17 +93,27 @@ typedef struct {
   int32_t zero_guess;        /* nonzero: start from x = 0 and ignore x's input contents */
   double* history;           /* HOST array, may be NULL: iterated relative residual per iteration */
   int32_t history_len;       /* capacity of history (entries beyond are dropped) */
+  int32_t profile;           /* nonzero (cg_solve only): time the inner loop's kernels with HIP
+                                events on `stream` over the first 64 iterations (see wd_cg_result) */
+  int32_t scheme;            /* WD_RELIABLE_UPDATE or WD_ITERATIVE_REFINEMENT (cg_solve, mixed) */
   int32_t pad;
+  double inner_tol;          /* residual reduction between FP64 recomputations; 0 -> the default
+                                (reliable updates: 0.1 BF16, 1e-2 FP16, 1e-4 FP32; refinement: 0.1) */
 } wd_cg_params;
 
 typedef struct {
   int32_t iterations;        /* iterations performed (inner iterations for mixed) */
   int32_t reliable_updates;  /* FP64 residual recomputations (mixed) */
   int32_t status;            /* same value as the call's return code */
-  int32_t pad;
+  int32_t two_row_links;     /* 1 if the inner iterations used two-row (12-real) links: cg_solve does
+                                so for WD_BF16 / WD_F16 on tileable lattices whose links are SU(3)
+                                to 1e-9 (checked on the device); 0 otherwise */
   double true_rel_res;       /* ||b' - D^+ D x|| / ||b'|| recomputed in FP64 at the end */
   double iter_rel_res;       /* the recurrence's own residual at the end */
   double seconds;            /* host wall time of the call */
+  double kernel_seconds[3];  /* with params->profile: average device time of one launch of the inner
+                                loop's (0) t = D p kernel, (1) fused D^+ t / r, x update kernel,
+                                (2) p = r + beta p kernel; 0 otherwise */
 } wd_cg_result;
 
 /* Thread-local text of the last non-zero return on the calling thread. */

@@ -18,10 +18,13 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "wilson.h")
 WD_F64, WD_F32, WD_BF16, WD_F16 = 0, 1, 2, 3
 WD_RHS_SOURCE, WD_RHS_NORMAL = 0, 1
 WD_C128, WD_C64 = 0, 1
+WD_TWO_ROW_LINKS = 0x100
+WD_RELIABLE_UPDATE, WD_ITERATIVE_REFINEMENT = 0, 1
 WD_OK, WD_NOT_CONVERGED = 0, 1
 WD_ERR_INVALID, WD_ERR_HIP, WD_ERR_BREAKDOWN, WD_ERR_NAN, WD_ERR_WORKSPACE = -1, -2, -3, -4, -5
 
-PREC_NAMES = {"f64": WD_F64, "f32": WD_F32, "bf16": WD_BF16, "f16": WD_F16}
+PREC_NAMES = {"f64": WD_F64, "f32": WD_F32, "bf16": WD_BF16, "f16": WD_F16,
+              "bf16_rows2": WD_BF16 | WD_TWO_ROW_LINKS, "f16_rows2": WD_F16 | WD_TWO_ROW_LINKS}
 
 
 class WdLattice(ctypes.Structure):
@@ -39,7 +42,10 @@ class WdCgParams(ctypes.Structure):
         ("zero_guess", ctypes.c_int32),
         ("history", ctypes.POINTER(ctypes.c_double)),
         ("history_len", ctypes.c_int32),
+        ("profile", ctypes.c_int32),
+        ("scheme", ctypes.c_int32),
         ("pad", ctypes.c_int32),
+        ("inner_tol", ctypes.c_double),
     ]
 
 
@@ -48,14 +54,17 @@ class WdCgResult(ctypes.Structure):
         ("iterations", ctypes.c_int32),
         ("reliable_updates", ctypes.c_int32),
         ("status", ctypes.c_int32),
-        ("pad", ctypes.c_int32),
+        ("two_row_links", ctypes.c_int32),
         ("true_rel_res", ctypes.c_double),
         ("iter_rel_res", ctypes.c_double),
         ("seconds", ctypes.c_double),
+        ("kernel_seconds", ctypes.c_double * 3),
     ]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "kernel_seconds"}
+        d["kernel_seconds"] = list(self.kernel_seconds)
+        return d
 
 
 _P = ctypes.c_void_p

@@ -147,18 +147,69 @@ int get_mirror(HostMirror** out) {
   return WD_OK;
 }
 
+// Events for params->profile: per device, 3 kernel kinds x kClockSamples
+// iterations x (begin, end), created on first use.
+constexpr int kClockSamples = 64;
+struct KernelClock {
+  EventPair ev[3][kClockSamples];
+  bool ready = false;
+};
+KernelClock g_clock[64];
+
+int get_clock(KernelClock** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(WD_ERR_HIP, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_mirror_mu);
+  KernelClock& c = g_clock[dev];
+  if (!c.ready) {
+    for (int k = 0; k < 3; ++k)
+      for (int i = 0; i < kClockSamples; ++i) {
+        HIP_TRY(hipEventCreate(&c.ev[k][i].begin));
+        HIP_TRY(hipEventCreate(&c.ev[k][i].end));
+      }
+    c.ready = true;
+  }
+  *out = &c;
+  return WD_OK;
+}
+
+// Event pair of kernel kind k at enqueued iteration i, or null when not sampled.
+const EventPair* clock_at(KernelClock* c, int k, int i) {
+  return (c && i < kClockSamples) ? &c->ev[k][i] : nullptr;
+}
+
+// Average device time per kernel kind over the sampled iterations (stream synchronised).
+void clock_read(KernelClock* c, int n, double out[3]) {
+  for (int k = 0; k < 3; ++k) out[k] = 0.0;
+  if (!c) return;
+  n = std::min(n, kClockSamples);
+  for (int k = 0; k < 3; ++k) {
+    double sum = 0.0;
+    int cnt = 0;
+    for (int i = 0; i < n; ++i) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, c->ev[k][i].begin, c->ev[k][i].end) == hipSuccess) {
+        sum += ms * 1e-3;
+        ++cnt;
+      }
+    }
+    out[k] = cnt ? sum / cnt : 0.0;
+  }
+}
+
 int fill_result(wd_cg_result* res, const SolverState& st, int code, double secs, double iter_rel) {
   if (!res) return code;
   res->iterations = st.iter;
   res->reliable_updates = st.rel_updates;
   res->status = code;
-  res->pad = 0;
   const double bn = st.bnorm2 > 0 ? st.bnorm2 : 1.0;
   res->true_rel_res = std::sqrt(st.rho_true / bn);
   res->iter_rel_res = iter_rel;
   res->seconds = secs;
   return code;
 }
+// (kernel_seconds is filled by the drivers before fill_result)
 
 int status_to_code(int status) {
   if (status == 1) return WD_OK;
@@ -178,6 +229,9 @@ int validate_params(const wd_cg_params* p) {
   if (p->io_dtype != WD_C128 && p->io_dtype != WD_C64) return fail(WD_ERR_INVALID, "io_dtype = %d unknown", p->io_dtype);
   if (p->history_len < 0) return fail(WD_ERR_INVALID, "history_len = %d", p->history_len);
   if (p->history_len > 0 && !p->history) return fail(WD_ERR_INVALID, "history is NULL but history_len > 0");
+  if (p->scheme != WD_RELIABLE_UPDATE && p->scheme != WD_ITERATIVE_REFINEMENT)
+    return fail(WD_ERR_INVALID, "scheme = %d unknown", p->scheme);
+  if (!(p->inner_tol >= 0.0 && p->inner_tol < 1.0)) return fail(WD_ERR_INVALID, "inner_tol = %g not in [0, 1)", p->inner_tol);
   return WD_OK;
 }
 
@@ -226,10 +280,27 @@ int wilson_apply_dagger(const wd_lattice* lat, double mass, const void* U, const
   return apply_common(lat, mass, U, psi, out, stream, 1);
 }
 
+// prec of a packed gauge field, possibly with WD_TWO_ROW_LINKS: returns the
+// precision, sets *rows2; fails unless two rows are asked for a 16-bit field on
+// a tiled lattice.
+static int gauge_format(const wd_lattice* lat, int32_t prec, int* rows2) {
+  *rows2 = (prec & WD_TWO_ROW_LINKS) ? 1 : 0;
+  const int p = prec & ~WD_TWO_ROW_LINKS;
+  if (!valid_prec(p)) return fail(WD_ERR_INVALID, "prec = %d unknown", prec);
+  if (*rows2 && !(p == WD_BF16 || p == WD_F16))
+    return fail(WD_ERR_INVALID, "two-row links exist for WD_BF16 and WD_F16 only");
+  if (*rows2 && !packed_geom(lat).tiled)
+    return fail(WD_ERR_INVALID, "two-row links need every lattice extent to be a multiple of 4");
+  return WD_OK;
+}
+
 size_t wd_gauge_bytes(const wd_lattice* lat, int32_t prec) {
   if (check_lattice(lat)) return 0;
-  if (!valid_prec(prec)) { fail(WD_ERR_INVALID, "prec = %d unknown", prec); return 0; }
-  return gauge_bytes(prec, packed_geom(lat).Vpad);
+  int rows2 = 0;
+  if (gauge_format(lat, prec, &rows2)) return 0;
+  const int p = prec & ~WD_TWO_ROW_LINKS;
+  const Geom g = packed_geom(lat);
+  return rows2 ? (size_t)g.Vpad * 4 * 6 * 4 : gauge_bytes(p, g.Vpad);
 }
 
 size_t wd_spinor_bytes(const wd_lattice* lat, int32_t prec) {
@@ -251,9 +322,12 @@ static SpinorBuf packed_view(const Geom& g, int prec, const void* p) {
 int wd_pack_gauge(const wd_lattice* lat, const void* U, int32_t prec, void* out, void* stream) {
   int rc = check_lattice(lat);
   if (rc) return rc;
-  if (!valid_prec(prec)) return fail(WD_ERR_INVALID, "prec = %d unknown", prec);
+  int rows2 = 0;
+  if ((rc = gauge_format(lat, prec, &rows2))) return rc;
   if (!U || !out) return fail(WD_ERR_INVALID, "NULL field pointer");
-  launch_pack_gauge(packed_geom(lat), U, prec, out, as_stream(stream));
+  const int p = prec & ~WD_TWO_ROW_LINKS;
+  if (rows2) launch_pack_gauge_rows2(packed_geom(lat), U, p, out, as_stream(stream));
+  else launch_pack_gauge(packed_geom(lat), U, p, out, as_stream(stream));
   HIP_TRY(hipGetLastError());
   return WD_OK;
 }
@@ -287,12 +361,14 @@ int wilson_apply_packed(const wd_lattice* lat, double mass, int32_t prec, const 
                         const void* in_packed, void* out_packed, int32_t dagger, void* stream) {
   int rc = check_lattice(lat);
   if (rc) return rc;
-  if (!valid_prec(prec)) return fail(WD_ERR_INVALID, "prec = %d unknown", prec);
+  int rows2 = 0;
+  if ((rc = gauge_format(lat, prec, &rows2))) return rc;
   if (!U_packed || !in_packed || !out_packed) return fail(WD_ERR_INVALID, "NULL field pointer");
   if (in_packed == out_packed) return fail(WD_ERR_INVALID, "in and out must not alias");
+  const int p = prec & ~WD_TWO_ROW_LINKS;
   const Geom g = packed_geom(lat);
-  launch_wilson_packed(g, prec, U_packed, packed_view(g, prec, in_packed), packed_view(g, prec, out_packed), mass,
-                       dagger ? 1 : 0, G_ALWAYS, F_NONE, nullptr, nullptr, as_stream(stream));
+  launch_wilson_packed(g, p, U_packed, packed_view(g, p, in_packed), packed_view(g, p, out_packed), mass,
+                       dagger ? 1 : 0, G_ALWAYS, F_NONE, nullptr, nullptr, as_stream(stream), nullptr, rows2);
   HIP_TRY(hipGetLastError());
   return WD_OK;
 }
@@ -410,6 +486,8 @@ int cg_plain(const Geom& g, double mass, const void* U, const void* b, void* x, 
 
   HostMirror* m;
   if ((rc = get_mirror(&m))) return rc;
+  KernelClock* clk = nullptr;
+  if (p->profile && (rc = get_clock(&clk))) return rc;
   Poller poll{m, nullptr, s};
   SolverState st{};
   st.stop2 = 1;
@@ -421,9 +499,12 @@ int cg_plain(const Geom& g, double mass, const void* U, const void* b, void* x, 
       const int n = next_chunk(st, enqueued, p->max_iter);
       if (n <= 0) break;
       for (int k = 0; k < n; ++k) {
-        launch_wilson_packed(g, P_F64, w.U64, w.p64, w.t64, mass, 0, G_ITER, F_ALPHA, w.st, w.partials, s);
-        launch_cg_update(g, P_F64, w.U64, w.t64, w.r64, w.p64, w.x64, mass, w.st, w.partials, s);
-        launch_p_update(g, w.r64, w.p64, w.st, s);
+        const int i = enqueued + k;
+        launch_wilson_packed(g, P_F64, w.U64, w.p64, w.t64, mass, 0, G_ITER, F_ALPHA, w.st, w.partials, s,
+                             clock_at(clk, 0, i));
+        launch_cg_update(g, P_F64, w.U64, w.t64, w.r64, w.p64, w.x64, mass, w.st, w.partials, s,
+                         clock_at(clk, 1, i));
+        launch_p_update(g, w.r64, w.p64, w.st, s, clock_at(clk, 2, i));
       }
       enqueued += n;
       HIP_TRY(hipGetLastError());
@@ -464,6 +545,7 @@ int cg_plain(const Geom& g, double mass, const void* U, const void* b, void* x, 
   if ((rc = copy_history(w, p, s, st.iter))) return rc;
   HIP_TRY(hipStreamSynchronize(s));
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (res) clock_read(clk, enqueued, res->kernel_seconds);
   int code;
   if (st.status < 0) code = status_to_code(st.status);
   else if (st.rho_true <= st.stop2) code = WD_OK;
@@ -478,22 +560,39 @@ int cg_plain(const Geom& g, double mass, const void* U, const void* b, void* x, 
 int cg_mixed(const Geom& g, double mass, const void* U, const void* b, void* x, const wd_cg_params* p,
              wd_cg_result* res, void* ws, hipStream_t s, std::chrono::steady_clock::time_point t0) {
   const int P = p->inner_prec;
-  const int interval = p->reliable_interval > 0 ? p->reliable_interval : 50;
+  const bool refine = p->scheme == WD_ITERATIVE_REFINEMENT;
+  // refinement: no periodic recomputation, only after each inner solve
+  const int interval = refine ? (1 << 30) : (p->reliable_interval > 0 ? p->reliable_interval : 50);
   const CgWorkspace w = layout_cg(ws, g, P, p->history_len);
   // Besides every `interval` iterations, recompute the residual whenever the
   // iterated residual has fallen by `delta` since the last update, so that
   // the low-precision drift (~ unit roundoff x the residual at the last
   // update) stays well below the residual being iterated.
-  const double delta = (P == WD_BF16) ? 0.1 : (P == WD_F16) ? 1e-2 : 1e-4;
+  double delta = (P == WD_BF16) ? 0.1 : (P == WD_F16) ? 1e-2 : 1e-4;
+  if (refine) delta = 0.1;
+  if (p->inner_tol > 0.0) delta = p->inner_tol;
   int rc = cg_setup(g, mass, U, b, x, p, w, interval, delta, w.rh, s);
+  if (refine) launch_set_restart(w.st, s);
   if (rc) return rc;
-  launch_pack_gauge(g, U, P, w.Ulow, s);
+  HostMirror* m;
+  if ((rc = get_mirror(&m))) return rc;
+  // 16-bit inner links: two rows per link (row 2 rebuilt from unitarity) when
+  // every link is SU(3) to 1e-9; the full 9 entries otherwise.
+  int rows2 = 0;
+  if ((P == WD_BF16 || P == WD_F16) && g.tiled) {
+    launch_su3_check(g, U, w.st, w.partials, s);
+    HIP_TRY(hipMemcpyAsync(m->buf[0], w.st, sizeof(SolverState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    rows2 = m->buf[0]->su3_dev <= 1e-9;
+  }
+  if (rows2) launch_pack_gauge_rows2(g, U, P, w.Ulow, s);
+  else launch_pack_gauge(g, U, P, w.Ulow, s);
   launch_zero(g, w.xh, G_ALWAYS, w.st, s);
   launch_convert(g, w.rh, w.ph, G_ALWAYS, w.st, s);
   HIP_TRY(hipGetLastError());
 
-  HostMirror* m;
-  if ((rc = get_mirror(&m))) return rc;
+  KernelClock* clk = nullptr;
+  if (p->profile && (rc = get_clock(&clk))) return rc;
   Poller poll{m, nullptr, s};
   SolverState st{};
   st.stop2 = 1;
@@ -504,14 +603,17 @@ int cg_mixed(const Geom& g, double mass, const void* U, const void* b, void* x, 
       int n = next_chunk(st, enqueued, p->max_iter);
       if (n <= 0) break;
       for (int k = 0; k < n; ++k) {
-        launch_wilson_packed(g, P, w.Ulow, w.ph, w.th, mass, 0, G_ITER, F_ALPHA, w.st, w.partials, s);
-        launch_cg_update(g, P, w.Ulow, w.th, w.rh, w.ph, w.xh, mass, w.st, w.partials, s);
+        const int i = enqueued + k;
+        launch_wilson_packed(g, P, w.Ulow, w.ph, w.th, mass, 0, G_ITER, F_ALPHA, w.st, w.partials, s,
+                             clock_at(clk, 0, i), rows2);
+        launch_cg_update(g, P, w.Ulow, w.th, w.rh, w.ph, w.xh, mass, w.st, w.partials, s, clock_at(clk, 1, i),
+                         rows2);
         if ((enqueued + k + 1) % slot_every == 0) {
           launch_accumulate(g, w.x64, w.xh, G_RELIABLE, w.st, s);
           launch_wilson_packed(g, P_F64, w.U64, w.x64, w.t64, mass, 0, G_RELIABLE, F_NONE, w.st, w.partials, s);
           launch_residual(g, w.U64, w.t64, w.b64, w.rh, mass, G_RELIABLE, F_RELIABLE, w.st, w.partials, s);
         }
-        launch_p_update(g, w.rh, w.ph, w.st, s);
+        launch_p_update(g, w.rh, w.ph, w.st, s, clock_at(clk, 2, i));
       }
       enqueued += n;
       HIP_TRY(hipGetLastError());
@@ -537,6 +639,10 @@ int cg_mixed(const Geom& g, double mass, const void* U, const void* b, void* x, 
   if ((rc = copy_history(w, p, s, st.iter))) return rc;
   HIP_TRY(hipStreamSynchronize(s));
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (res) {
+    clock_read(clk, enqueued, res->kernel_seconds);
+    res->two_row_links = rows2;
+  }
   int code;
   if (st.status < 0) code = status_to_code(st.status);
   else if (st.rho_true <= st.stop2) code = WD_OK;

@@ -606,7 +606,7 @@ int batched_solve(const Geom& g, double mass, const void* U, int nrhs, const voi
       res[k].iterations = st.iter;
       res[k].reliable_updates = st.rel_updates;
       res[k].status = ck;
-      res[k].pad = 0;
+      res[k].two_row_links = 0;
       res[k].true_rel_res = std::sqrt(st.rho_true / bn);
       res[k].iter_rel_res = std::sqrt(st.rho / bn);
       res[k].seconds = secs;

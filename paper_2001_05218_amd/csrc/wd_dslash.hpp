@@ -78,6 +78,22 @@ __device__ __forceinline__ void reconstruct_add(R acc[24], const R w[12]) {
   }
 }
 
+// Row 2 of an SU(3) matrix from rows 0 and 1: u2_k = conj(u0_i u1_j - u0_j u1_i),
+// (i, j, k) cyclic (unitarity with unit determinant).
+template <typename R>
+__device__ __forceinline__ void su3_third_row(R u[18]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int i = (k + 1) % 3, j = (k + 2) % 3;
+    const R ar = u[2 * i] * u[2 * (3 + j)] - u[2 * i + 1] * u[2 * (3 + j) + 1];
+    const R ai = u[2 * i] * u[2 * (3 + j) + 1] + u[2 * i + 1] * u[2 * (3 + j)];
+    const R br = u[2 * j] * u[2 * (3 + i)] - u[2 * j + 1] * u[2 * (3 + i) + 1];
+    const R bi = u[2 * j] * u[2 * (3 + i) + 1] + u[2 * j + 1] * u[2 * (3 + i)];
+    u[2 * (6 + k)] = ar - br;
+    u[2 * (6 + k) + 1] = -(ai - bi);
+  }
+}
+
 // w = U h (ADJ = false) or U^+ h (ADJ = true), for both spin rows of h.
 template <bool ADJ, typename R>
 __device__ __forceinline__ void su3_mul_half(const R u[18], const R h[12], R w[12]) {

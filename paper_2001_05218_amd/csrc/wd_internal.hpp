@@ -23,6 +23,7 @@ struct SolverState {
   double stop2;      // (tol ||b'||)^2
   double rho_true;   // ||b' - D^+ D x||^2 from the last FP64 recomputation
   double rho_update; // rho right after the last reliable update (or at the start)
+  double su3_dev;    // largest deviation of a link from SU(3) (F_SU3MAX)
   double delta2;     // mixed: also update once rho <= delta2 * rho_update
   int iter;          // inner iterations completed
   int status;        // 0 running, 1 converged, -3 breakdown, -4 NaN/Inf
@@ -30,6 +31,7 @@ struct SolverState {
   int last_update;   // iteration of the last reliable update
   int interval;      // reliable-update interval (mixed)
   int rel_updates;   // reliable updates performed
+  int restart_on_update;  // refinement: every FP64 recomputation restarts the Krylov space (beta = 0)
   int hist_len;      // capacity of hist
   int pad0;
   unsigned int pad2;
@@ -58,6 +60,14 @@ enum Fin : int {
   F_RELIABLE = 5,  // rho_true = sum; converged? else rho = sum, beta = rho / rho_prev
                    //   (beta = 0, a restart, if the true residual exceeds twice the iterated one)
   F_TRUE = 6,      // rho_true = sum (final recomputation)
+  F_SU3MAX = 7,    // su3_dev = max of the partials (the finalize takes a maximum, not a sum)
+};
+
+// Optional pair of events recorded on the launch stream right before and
+// right after a kernel (not around its finalize kernel).
+struct EventPair {
+  hipEvent_t begin;
+  hipEvent_t end;
 };
 
 struct SpinorBuf {
@@ -72,6 +82,8 @@ void launch_init_state(SolverState* st, double tol, int interval, double delta, 
                        hipStream_t s);
 // Continue after a failed final check: status = 0, rho = rho_true.
 void launch_restart(SolverState* st, hipStream_t s);
+// Make every reliable update a restart (iterative refinement).
+void launch_set_restart(SolverState* st, hipStream_t s);
 void launch_pack_gauge(const Geom& g, const void* U_c128, int prec, void* out, hipStream_t s);
 void launch_pack_spinor(const Geom& g, const void* in, int io_c64, SpinorBuf out, hipStream_t s);
 void launch_unpack_spinor(const Geom& g, SpinorBuf in, void* out, int io_c64, hipStream_t s);
@@ -83,15 +95,23 @@ void launch_wilson_canonical(const Geom& g, const void* U, const void* in, void*
                              hipStream_t s);
 // out = D in / D^+ in on packed fields of one precision; optional reduction of ||out||^2.
 void launch_wilson_packed(const Geom& g, int prec, const void* U, SpinorBuf in, SpinorBuf out, double mass,
-                          int dagger, int gate, int fin, SolverState* st, double* partials, hipStream_t s);
+                          int dagger, int gate, int fin, SolverState* st, double* partials, hipStream_t s,
+                          const EventPair* ev = nullptr, int rows2 = 0);
+// Two-row (12-real) 16-bit gauge copy (BF16 or FP16), tiled lattices; the
+// tiled 16-bit kernels rebuild row 2 from unitarity (rows2 = 1).
+void launch_pack_gauge_rows2(const Geom& g, const void* U_c128, int prec, void* out, hipStream_t s);
+// su3_dev = largest deviation of a canonical complex128 gauge field from SU(3).
+void launch_su3_check(const Geom& g, const void* U_c128, SolverState* st, double* partials, hipStream_t s);
 // q = D^+ t (never stored); r -= alpha q; x += alpha p; ||r||^2 -> F_BETA.
 void launch_cg_update(const Geom& g, int prec, const void* U, SpinorBuf t, SpinorBuf r, SpinorBuf p, SpinorBuf x,
-                      double mass, SolverState* st, double* partials, hipStream_t s);
+                      double mass, SolverState* st, double* partials, hipStream_t s, const EventPair* ev = nullptr,
+                      int rows2 = 0);
 // out = low(b - D^+ t) with FP64 arithmetic on FP64 fields; ||b - D^+ t||^2 -> fin.
 void launch_residual(const Geom& g, const void* U64, SpinorBuf t64, SpinorBuf b64, SpinorBuf out, double mass,
                      int gate, int fin, SolverState* st, double* partials, hipStream_t s);
 // p = r + beta p
-void launch_p_update(const Geom& g, SpinorBuf r, SpinorBuf p, SolverState* st, hipStream_t s);
+void launch_p_update(const Geom& g, SpinorBuf r, SpinorBuf p, SolverState* st, hipStream_t s,
+                     const EventPair* ev = nullptr);
 // x(FP64) += xhat; xhat = 0
 void launch_accumulate(const Geom& g, SpinorBuf x64, SpinorBuf xhat, int gate, SolverState* st, hipStream_t s);
 // ||v||^2 -> fin

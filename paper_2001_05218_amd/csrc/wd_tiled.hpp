@@ -43,10 +43,19 @@ struct TileLds {
   float scale[kTileSlots];
 };
 
+// Links are stored either as all 9 entries (18 reals) or, for SU(3) fields,
+// as rows 0 and 1 only (12 reals; row 2 = conj(row0 x row1) is rebuilt on use).
+template <bool C12> struct LinkFormat {
+  static constexpr int entries = C12 ? 6 : 9;    // stored entries per link
+  static constexpr int words = 4 * entries;      // per site, 4 directions
+};
+
 // Stage the tile's spinors and halo faces; prefetch the 8 links of site s.
-template <int P>
+template <int P, bool C12>
 __device__ __forceinline__ void tile_stage(const Geom& g, int T, const void* Uv, const SpinorBuf& in, TileLds<P>& lds,
                                            uint32_t lk[8][9]) {
+  constexpr int NE = LinkFormat<C12>::entries;
+  constexpr int NW = LinkFormat<C12>::words;
   const int l = threadIdx.x;
   const int s = T * kTileSites + l;
   const uint32_t* U = static_cast<const uint32_t*>(Uv);
@@ -55,11 +64,11 @@ __device__ __forceinline__ void tile_stage(const Geom& g, int T, const void* Uv,
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu)
 #pragma unroll
-    for (int e = 0; e < 9; ++e) lk[mu][e] = U[word_index(s, 36, mu * 9 + e)];
+    for (int e = 0; e < NE; ++e) lk[mu][e] = U[word_index(s, NW, mu * NE + e)];
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu)
 #pragma unroll
-    for (int e = 0; e < 9; ++e) lk[4 + mu][e] = U[word_index(nb.bwd[mu], 36, mu * 9 + e)];
+    for (int e = 0; e < NE; ++e) lk[4 + mu][e] = U[word_index(nb.bwd[mu], NW, mu * NE + e)];
 #pragma unroll
   for (int w = 0; w < 3; ++w) lds.w[w][l] = src[word_index(s, 3, w)];
   if constexpr (P == P_F16) lds.scale[l] = in.scale[s];
@@ -94,17 +103,19 @@ __device__ __forceinline__ void tile_spinor(const TileLds<P>& lds, int slot, flo
 // Unpack a prefetched link at its point of use. The empty asm makes each raw
 // word opaque here, so the compiler cannot unpack all eight links right after
 // their loads (which would keep 144 floats live instead of 72 raw words).
-template <int P>
+template <int P, bool C12>
 __device__ __forceinline__ void link_from(const uint32_t raw[9], float u[18]) {
+  constexpr int NE = LinkFormat<C12>::entries;
 #pragma unroll
-  for (int e = 0; e < 9; ++e) {
+  for (int e = 0; e < NE; ++e) {
     uint32_t r = raw[e];
     asm volatile("" : "+v"(r));
     unpack_link16<P>(r, u[2 * e], u[2 * e + 1]);
   }
+  if constexpr (C12) su3_third_row(u);
 }
 
-template <int P, int MU, bool DAG>
+template <int P, bool C12, int MU, bool DAG>
 __device__ __forceinline__ void tile_hop(const TileLds<P>& lds, const uint32_t lk[8][9], int l, float acc[24]) {
   constexpr int SF = DAG ? +1 : -1;
   constexpr int SB = -SF;
@@ -115,12 +126,12 @@ __device__ __forceinline__ void tile_hop(const TileLds<P>& lds, const uint32_t l
   const int slot_b = (lm > 0) ? l - ls : kTileSites + (2 * MU + 1) * 64 + fp;
   float psi[24], h[12], w[12], u[18];
   tile_spinor<P>(lds, slot_f, psi);
-  link_from<P>(lk[MU], u);
+  link_from<P, C12>(lk[MU], u);
   project<MU, SF>(psi, h);
   su3_mul_half<false>(u, h, w);
   reconstruct_add<MU, SF>(acc, w);
   tile_spinor<P>(lds, slot_b, psi);
-  link_from<P>(lk[4 + MU], u);
+  link_from<P, C12>(lk[4 + MU], u);
   project<MU, SB>(psi, h);
   su3_mul_half<true>(u, h, w);
   reconstruct_add<MU, SB>(acc, w);
@@ -130,17 +141,17 @@ __device__ __forceinline__ void tile_hop(const TileLds<P>& lds, const uint32_t l
 }
 
 // out = D in (or D^+ in) at this thread's site of tile T, after tile_stage and a barrier.
-template <int P, bool DAG>
+template <int P, bool C12, bool DAG>
 __device__ __forceinline__ void tile_wilson(const TileLds<P>& lds, const uint32_t lk[8][9], float diag,
                                             float out[24]) {
   const int l = threadIdx.x;
   float acc[24];
 #pragma unroll
   for (int i = 0; i < 24; ++i) acc[i] = 0.f;
-  tile_hop<P, 0, DAG>(lds, lk, l, acc);
-  tile_hop<P, 1, DAG>(lds, lk, l, acc);
-  tile_hop<P, 2, DAG>(lds, lk, l, acc);
-  tile_hop<P, 3, DAG>(lds, lk, l, acc);
+  tile_hop<P, C12, 0, DAG>(lds, lk, l, acc);
+  tile_hop<P, C12, 1, DAG>(lds, lk, l, acc);
+  tile_hop<P, C12, 2, DAG>(lds, lk, l, acc);
+  tile_hop<P, C12, 3, DAG>(lds, lk, l, acc);
   float c[24];
   tile_spinor<P>(lds, l, c);
 #pragma unroll

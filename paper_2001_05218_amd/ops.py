@@ -12,7 +12,12 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import WD_C64, WD_C128, WD_F64, WD_RHS_NORMAL, WD_RHS_SOURCE, PREC_NAMES
+from ._lib import WD_C64, WD_C128, WD_F64, WD_RHS_NORMAL, WD_RHS_SOURCE, WD_TWO_ROW_LINKS, PREC_NAMES
+
+
+def _spinor_prec(prec: str) -> int:
+    """Spinor storage of a precision name (the two-row flag concerns links only)."""
+    return PREC_NAMES[prec] & ~WD_TWO_ROW_LINKS
 
 
 def _stream(device) -> ctypes.c_void_p:
@@ -85,7 +90,7 @@ def wilson_force(a: torch.Tensor, b: torch.Tensor, coeff: float = 1.0, out: torc
 
 
 def make_params(tol=1e-10, max_iter=10000, inner="f64", reliable_interval=50, rhs="source", io_dtype=WD_C128,
-                zero_guess=True, history_len=0):
+                zero_guess=True, history_len=0, profile=False, scheme="reliable", inner_tol=0.0):
     p = _lib.WdCgParams()
     p.tol = float(tol)
     p.max_iter = int(max_iter)
@@ -99,6 +104,9 @@ def make_params(tol=1e-10, max_iter=10000, inner="f64", reliable_interval=50, rh
         hist = (ctypes.c_double * int(history_len))()
         p.history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
     p.history_len = int(history_len)
+    p.profile = 1 if profile else 0
+    p.scheme = {"reliable": 0, "refinement": 1}[scheme] if isinstance(scheme, str) else int(scheme)
+    p.inner_tol = float(inner_tol)
     return p, hist
 
 
@@ -112,16 +120,21 @@ def workspace_bytes(dims, params, nrhs=1) -> int:
 
 def cg_solve(U: torch.Tensor, b: torch.Tensor, mass: float, tol: float = 1e-10, max_iter: int = 10000,
              inner: str = "f64", reliable_interval: int = 50, rhs: str = "source", x0: torch.Tensor | None = None,
-             history: int = 0, workspace: torch.Tensor | None = None, raise_on_nonconvergence: bool = True):
+             history: int = 0, workspace: torch.Tensor | None = None, raise_on_nonconvergence: bool = True,
+             profile: bool = False, scheme: str = "reliable", inner_tol: float = 0.0):
     """Solve D^+ D x = D^+ b (rhs="source") or D^+ D x = b (rhs="normal").
 
     Returns (x, info); info holds the wd_cg_result fields (and "history" if
-    asked). complex64 b gives complex64 x (inner arithmetic unchanged)."""
+    asked). complex64 b gives complex64 x (inner arithmetic unchanged).
+    profile=True fills info["kernel_seconds"] with the inner loop's average
+    kernel times. scheme="refinement" selects iterative refinement (defect
+    correction) instead of reliable updates for a mixed solve."""
     dims = dims_of_spinor(b)
     _need(b, "b", (torch.complex128, torch.complex64), spinor_shape(dims))
     _need(U, "U", (torch.complex128,), gauge_shape(dims))
     io = WD_C64 if b.dtype == torch.complex64 else WD_C128
-    params, hist = make_params(tol, max_iter, inner, reliable_interval, rhs, io, x0 is None, history)
+    params, hist = make_params(tol, max_iter, inner, reliable_interval, rhs, io, x0 is None, history, profile,
+                               scheme, inner_tol)
     if x0 is None:
         x = torch.empty_like(b)
     else:
@@ -185,7 +198,10 @@ def pack_gauge(U: torch.Tensor, prec: str = "f64") -> torch.Tensor:
     lib = _lib.load()
     lat = _lib.lattice(dims)
     p = PREC_NAMES[prec]
-    out = torch.empty(int(lib.wd_gauge_bytes(ctypes.byref(lat), p)), dtype=torch.uint8, device=U.device)
+    n = int(lib.wd_gauge_bytes(ctypes.byref(lat), p))
+    if n == 0:
+        raise _lib.WilsonError(_lib.WD_ERR_INVALID, "wd_gauge_bytes", _lib.last_error())
+    out = torch.empty(n, dtype=torch.uint8, device=U.device)
     _lib.check(lib.wd_pack_gauge(ctypes.byref(lat), U.data_ptr(), p, out.data_ptr(), _stream(U.device)),
                "wd_pack_gauge")
     return out
@@ -196,7 +212,7 @@ def pack_spinor(psi: torch.Tensor, prec: str = "f64") -> torch.Tensor:
     _need(psi, "psi", (torch.complex128, torch.complex64), spinor_shape(dims))
     lib = _lib.load()
     lat = _lib.lattice(dims)
-    p = PREC_NAMES[prec]
+    p = _spinor_prec(prec)
     out = torch.empty(int(lib.wd_spinor_bytes(ctypes.byref(lat), p)), dtype=torch.uint8, device=psi.device)
     io = WD_C64 if psi.dtype == torch.complex64 else WD_C128
     _lib.check(lib.wd_pack_spinor(ctypes.byref(lat), psi.data_ptr(), io, p, out.data_ptr(), _stream(psi.device)),
@@ -207,7 +223,7 @@ def pack_spinor(psi: torch.Tensor, prec: str = "f64") -> torch.Tensor:
 def unpack_spinor(packed: torch.Tensor, dims, prec: str = "f64", dtype=torch.complex128) -> torch.Tensor:
     lib = _lib.load()
     lat = _lib.lattice(dims)
-    p = PREC_NAMES[prec]
+    p = _spinor_prec(prec)
     out = torch.empty(spinor_shape(dims), dtype=dtype, device=packed.device)
     io = WD_C64 if dtype == torch.complex64 else WD_C128
     _lib.check(lib.wd_unpack_spinor(ctypes.byref(lat), packed.data_ptr(), p, out.data_ptr(), io,
@@ -217,7 +233,7 @@ def unpack_spinor(packed: torch.Tensor, dims, prec: str = "f64", dtype=torch.com
 
 def empty_packed_spinor(dims, prec: str, device) -> torch.Tensor:
     lib = _lib.load()
-    n = int(lib.wd_spinor_bytes(ctypes.byref(_lib.lattice(dims)), PREC_NAMES[prec]))
+    n = int(lib.wd_spinor_bytes(ctypes.byref(_lib.lattice(dims)), _spinor_prec(prec)))
     return torch.empty(n, dtype=torch.uint8, device=device)
 
 

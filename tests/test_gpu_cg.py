@@ -143,3 +143,55 @@ def test_deterministic_history(inner):
     assert a["iterations"] == c["iterations"]
     assert a["history"] == c["history"]
     assert a["true_rel_res"] == c["true_rel_res"]
+
+
+@pytest.mark.parametrize("inner", ["f64", "f16"])
+def test_profile_reports_kernel_times(inner):
+    dims = (16, 16, 16, 32)
+    U, b = _fields(dims, "near_identity", 101)
+    Ut, bt = to_dev(U), to_dev(b)
+    _, plain = wd.cg_solve(Ut, bt, 0.05, tol=1e-8, inner=inner)
+    x, info = wd.cg_solve(Ut, bt, 0.05, tol=1e-8, inner=inner, profile=True)
+    assert plain["kernel_seconds"] == [0.0, 0.0, 0.0]
+    ks = info["kernel_seconds"]
+    assert all(k > 0 for k in ks)
+    # the fused D^+ update moves more bytes than D, which moves more than the p update
+    assert ks[1] > ks[0] > ks[2]
+    # profiling does not change the arithmetic
+    assert info["iterations"] == plain["iterations"]
+
+
+def test_mixed_two_row_links_only_for_su3():
+    dims = (8, 8, 8, 8)
+    U, b = _fields(dims, "near_identity", 111)
+    Ut, bt = to_dev(U), to_dev(b)
+    x, info = wd.cg_solve(Ut, bt, 0.05, tol=TOL, inner="f16")
+    assert info["two_row_links"] == 1
+    assert _true_res(U, to_np(x), b, 0.05) <= TOL * (1 + 1e-3)
+    # links slightly off SU(3): the solver must keep all nine entries
+    U2 = U * 1.001
+    x2, info2 = wd.cg_solve(to_dev(U2), bt, 0.05, tol=TOL, inner="f16")
+    assert info2["two_row_links"] == 0
+    assert _true_res(U2, to_np(x2), b, 0.05) <= TOL * (1 + 1e-3)
+    # linear site order (extent not a multiple of 4): full links
+    dims3 = (6, 4, 4, 4)
+    U3, b3 = _fields(dims3, "near_identity", 112)
+    x3, info3 = wd.cg_solve(to_dev(U3), to_dev(b3), 0.05, tol=TOL, inner="bf16")
+    assert info3["two_row_links"] == 0
+    assert _true_res(U3, to_np(x3), b3, 0.05) <= TOL * (1 + 1e-3)
+
+
+@pytest.mark.parametrize("inner", ["f16", "bf16", "f32"])
+def test_iterative_refinement(inner):
+    # defect correction: each cycle restarts an inner low-precision solve on the FP64 residual
+    dims = (8, 8, 8, 16)
+    U, b = _fields(dims, "near_identity", 71)
+    Ut, bt = to_dev(U), to_dev(b)
+    x, info = wd.cg_solve(Ut, bt, 0.02, tol=TOL, inner=inner, scheme="refinement", inner_tol=0.1)
+    res = _true_res(U, to_np(x), b, 0.02)
+    log(f"  refinement {inner}: iterations={info['iterations']} cycles={info['reliable_updates']} res={res:.2e}")
+    assert res <= TOL * (1 + 1e-3)
+    assert info["reliable_updates"] >= 5          # ~one decade per cycle
+    _, ru = wd.cg_solve(Ut, bt, 0.02, tol=TOL, inner=inner)
+    # restarts lose the Krylov history: never fewer iterations than reliable updates
+    assert info["iterations"] >= ru["iterations"]

@@ -96,3 +96,29 @@ def test_adjoint_identity_on_gpu():
     lhs = (a.conj() * wd.wilson_apply(U, b, 0.1)).sum().item()
     rhs = (wd.wilson_apply(U, a, 0.1, dagger=True).conj() * b).sum().item()
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+@pytest.mark.parametrize("prec,bound", [("bf16_rows2", 1.5e-2), ("f16_rows2", 3e-3)])
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (8, 4, 4, 8)])
+def test_two_row_links_parity(dims, prec, bound):
+    # SU(3) links stored as two rows, the third rebuilt on the fly
+    U = fieldgen.gauge_field(dims, "haar", 51)
+    psi = fieldgen.gaussian_spinor(dims, 52)
+    Ut, pt = to_dev(U), to_dev(psi)
+    Up = wd.pack_gauge(Ut, prec)
+    full = wd.pack_gauge(Ut, prec.split("_")[0])
+    assert Up.numel() * 3 == full.numel() * 2
+    pin = wd.pack_spinor(pt, prec)
+    for dagger in (False, True):
+        pout = wd.empty_packed_spinor(dims, prec, pt.device)
+        wd.wilson_apply_packed(Up, pin, pout, dims, 0.1, prec, dagger)
+        out = to_np(wd.unpack_spinor(pout, dims, prec))
+        ref = (oracle.wilson_Ddag if dagger else oracle.wilson_D)(U, psi, 0.1)
+        assert rel(out, ref) <= bound
+
+
+def test_two_row_links_rejected_where_undefined():
+    from paper_2001_05218_amd import _lib
+    U = to_dev(fieldgen.gauge_field((6, 4, 4, 4), "haar", 1))
+    with pytest.raises(_lib.WilsonError):
+        wd.pack_gauge(U, "f16_rows2")      # 6 is not a multiple of 4

@@ -38,8 +38,8 @@ def test_required_boundary_calls_present():
 def test_struct_layouts_match_header():
     # sizes of the structs as laid out by a C compiler for the header
     assert ctypes.sizeof(_lib.WdLattice) == 16
-    assert ctypes.sizeof(_lib.WdCgParams) == 48
-    assert ctypes.sizeof(_lib.WdCgResult) == 40
+    assert ctypes.sizeof(_lib.WdCgParams) == 64
+    assert ctypes.sizeof(_lib.WdCgResult) == 64
 
 
 def _lat(dims):
@@ -56,6 +56,8 @@ def _params(**kw):
     p.io_dtype = kw.get("io_dtype", 0)
     p.zero_guess = 1
     p.history_len = kw.get("history_len", 0)
+    p.scheme = kw.get("scheme", 0)
+    p.inner_tol = kw.get("inner_tol", 0.0)
     return p
 
 
@@ -87,6 +89,7 @@ def test_force_rejects_bad_args(lib):
     (dict(tol=0.0), "tol"), (dict(tol=-1.0), "tol"), (dict(max_iter=0), "max_iter"),
     (dict(inner_prec=7), "inner_prec"), (dict(rhs_mode=3), "rhs_mode"), (dict(io_dtype=5), "io_dtype"),
     (dict(reliable_interval=-1), "reliable_interval"), (dict(history_len=4), "history"),
+    (dict(scheme=2), "scheme"), (dict(inner_tol=1.5), "inner_tol"), (dict(inner_tol=-0.1), "inner_tol"),
 ])
 def test_cg_rejects_bad_params(lib, kw, msg):
     p = _params(**kw)
