@@ -43,9 +43,13 @@ TOL = 1e-10
 BYTES_PER_SITE = {"f64": 4 * 9 * 16 + 2 * 192, "f32": 4 * 9 * 8 + 2 * 96, "bf16": 4 * 9 * 4 + 2 * 48,
                   "f16": 4 * 9 * 4 + 2 * 48 + 2 * 4}
 FLOPS_PER_SITE = 1368
-# algorithmic bytes per site of the inner loop's three kernels, by storage:
+# algorithmic bytes per site of the inner loop's kernels, by storage:
 #   D p       : 4 links + p in + t out
-#   update    : 4 links + t in (D^+ t) + r in/out + p in + x(hat) in/out (FP32, FP64 for plain CG)
+#   update    : 4 links + t in (D^+ t) + r in/out
+#               (plain FP64 CG also p in + x in/out; the mixed solver keeps each
+#               iteration's p in a ring and folds sum alpha_j p_j into the FP64 x
+#               at reliable updates: per iteration one more read of p plus
+#               1/len of an FP64 x read and write, outside these kernels)
 #   p update  : r in + p in + p out
 SPINOR_B = {"f64": 192, "f32": 96, "bf16": 48, "f16": 52}
 LINKS_B = {"f64": 576, "f32": 288, "bf16": 144, "f16": 144}
@@ -57,8 +61,8 @@ def loop_kernel_bytes(prec, two_row_links=False):
     sp, lk = SPINOR_B[prec], LINKS_B[prec]
     if two_row_links:
         lk = lk * 2 // 3
-    xb = 2 * (192 if prec == "f64" else 96)
-    return {"D": lk + 2 * sp, "update": lk + sp + 2 * sp + sp + xb, "p_update": 3 * sp}
+    upd = lk + 3 * sp + (sp + 2 * 192 if prec == "f64" else 0)
+    return {"D": lk + 2 * sp, "update": upd, "p_update": 3 * sp}
 
 
 KERNEL_NAMES = {  # kernel that runs each loop step for a storage precision (tiled lattice)
@@ -322,7 +326,7 @@ def main():
     rows2 = bool(infos[-1]["two_row_links"])
     kb = loop_kernel_bytes(best, rows2)
     loop = {}
-    for j, kind in enumerate(("D", "update", "p_update")):
+    for j, kind in enumerate(kb):
         secs = float(np.mean([i["kernel_seconds"][j] for i in infos]))
         gbs = kb[kind] * V / secs / 1e9 if secs > 0 else 0.0
         name = KERNEL_NAMES[kind][best] + ("_rows2" if rows2 and kind != "p_update" else "")

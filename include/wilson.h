@@ -96,7 +96,11 @@ typedef struct {
   int32_t profile;           /* nonzero (cg_solve only): time the inner loop's kernels with HIP
                                 events on `stream` over the first 64 iterations (see wd_cg_result) */
   int32_t scheme;            /* WD_RELIABLE_UPDATE or WD_ITERATIVE_REFINEMENT (cg_solve, mixed) */
-  int32_t pad;
+  int32_t ring_len;          /* mixed (cg_solve): search directions kept in the workspace before
+                                they are folded into x (x += sum alpha_j p_j, in FP64); 0 -> 32,
+                                else 8..256. The fold runs at each FP64 recomputation and
+                                whenever ring_len - 4 directions are pending. Workspace grows by
+                                ring_len low-precision spinors. */
   double inner_tol;          /* residual reduction between FP64 recomputations; 0 -> the default
                                 (reliable updates: 0.1 BF16, 1e-2 FP16, 1e-4 FP32; refinement: 0.1) */
 } wd_cg_params;
@@ -112,8 +116,8 @@ typedef struct {
   double iter_rel_res;       /* the recurrence's own residual at the end */
   double seconds;            /* host wall time of the call */
   double kernel_seconds[3];  /* with params->profile: average device time of one launch of the inner
-                                loop's (0) t = D p kernel, (1) fused D^+ t / r, x update kernel,
-                                (2) p = r + beta p kernel; 0 otherwise */
+                                loop's (0) t = D p kernel, (1) fused D^+ t / r update kernel (plain
+                                FP64 CG: also x += alpha p), (2) p = r + beta p kernel; 0 otherwise */
 } wd_cg_result;
 
 /* Thread-local text of the last non-zero return on the calling thread. */

@@ -44,7 +44,7 @@ class WdCgParams(ctypes.Structure):
         ("history_len", ctypes.c_int32),
         ("profile", ctypes.c_int32),
         ("scheme", ctypes.c_int32),
-        ("pad", ctypes.c_int32),
+        ("ring_len", ctypes.c_int32),
         ("inner_tol", ctypes.c_double),
     ]
 

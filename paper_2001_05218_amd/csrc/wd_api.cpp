@@ -95,11 +95,18 @@ struct CgWorkspace {
   void* U64;
   void* Ulow;
   SpinorBuf b64, x64, r64, p64, t64;   // plain FP64 CG (r64/p64 unused by mixed)
-  SpinorBuf ph, rh, th, xh;             // mixed: low-precision p, r, t; FP32 x-hat
+  SpinorBuf rh, th;                     // mixed: low-precision r, t
+  RingBuf ring;                         // mixed: search directions since the last x update
+  double* alpha_hist;                   // mixed: their alphas
   size_t bytes;
 };
 
-CgWorkspace layout_cg(void* base, const Geom& g, int inner, int hist_len) {
+constexpr int kDefaultRing = 32;
+constexpr int kSlotEvery = 5;   // mixed: a reliable-update slot after every 5th enqueued iteration
+
+int ring_length(const wd_cg_params* p) { return p->ring_len > 0 ? p->ring_len : kDefaultRing; }
+
+CgWorkspace layout_cg(void* base, const Geom& g, int inner, int hist_len, int ring_len) {
   Carver c(base);
   CgWorkspace w{};
   w.st = static_cast<SolverState*>(c.take(sizeof(SolverState)));
@@ -114,10 +121,17 @@ CgWorkspace layout_cg(void* base, const Geom& g, int inner, int hist_len) {
     w.p64 = take_spinor(c, P_F64, g);
   } else {
     w.Ulow = c.take(gauge_bytes(inner, g.Vpad));
-    w.ph = take_spinor(c, inner, g);
     w.rh = take_spinor(c, inner, g);
     w.th = take_spinor(c, inner, g);
-    w.xh = take_spinor(c, P_F32, g);
+    w.alpha_hist = static_cast<double*>(c.take(sizeof(double) * (size_t)ring_len));
+    w.ring.prec = inner;
+    w.ring.len = ring_len;
+    w.ring.stride = (long long)align_up(spinor_bytes(inner, g.Vpad));
+    w.ring.data = static_cast<char*>(c.take((size_t)w.ring.stride * ring_len));
+    if (inner == WD_F16) {
+      w.ring.scale_stride = (long long)align_up(spinor_scale_bytes(inner, g.Vpad));
+      w.ring.scale = static_cast<char*>(c.take((size_t)w.ring.scale_stride * ring_len));
+    }
   }
   w.bytes = c.off;
   return w;
@@ -179,12 +193,13 @@ const EventPair* clock_at(KernelClock* c, int k, int i) {
   return (c && i < kClockSamples) ? &c->ev[k][i] : nullptr;
 }
 
-// Average device time per kernel kind over the sampled iterations (stream synchronised).
-void clock_read(KernelClock* c, int n, double out[3]) {
+// Average device time per kernel kind over the sampled iterations (stream
+// synchronised); kinds beyond `kinds` were not launched and read 0.
+void clock_read(KernelClock* c, int n, int kinds, double out[3]) {
   for (int k = 0; k < 3; ++k) out[k] = 0.0;
   if (!c) return;
   n = std::min(n, kClockSamples);
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < kinds; ++k) {
     double sum = 0.0;
     int cnt = 0;
     for (int i = 0; i < n; ++i) {
@@ -215,6 +230,7 @@ int status_to_code(int status) {
   if (status == 1) return WD_OK;
   if (status == -3) return fail(WD_ERR_BREAKDOWN, "CG breakdown: <p, D^+D p> <= 0");
   if (status == -4) return fail(WD_ERR_NAN, "NaN or Inf encountered in a CG reduction");
+  if (status == -5) return fail(WD_ERR_HIP, "internal: search-direction ring overflow");
   return WD_OK;
 }
 
@@ -232,6 +248,8 @@ int validate_params(const wd_cg_params* p) {
   if (p->scheme != WD_RELIABLE_UPDATE && p->scheme != WD_ITERATIVE_REFINEMENT)
     return fail(WD_ERR_INVALID, "scheme = %d unknown", p->scheme);
   if (!(p->inner_tol >= 0.0 && p->inner_tol < 1.0)) return fail(WD_ERR_INVALID, "inner_tol = %g not in [0, 1)", p->inner_tol);
+  if (p->ring_len != 0 && (p->ring_len < 8 || p->ring_len > 256))
+    return fail(WD_ERR_INVALID, "ring_len = %d must be 0 or in [8, 256]", p->ring_len);
   return WD_OK;
 }
 
@@ -239,7 +257,8 @@ int validate_params(const wd_cg_params* p) {
 // single-system cg_solve_batched.
 size_t required_bytes(const Geom& g, const wd_cg_params* p, int nrhs) {
   const size_t batched = batched_workspace_bytes(g, nrhs, p->history_len);
-  if (nrhs == 1) return std::max(layout_cg(nullptr, g, p->inner_prec, p->history_len).bytes, batched);
+  if (nrhs == 1)
+    return std::max(layout_cg(nullptr, g, p->inner_prec, p->history_len, ring_length(p)).bytes, batched);
   return batched;
 }
 
@@ -479,7 +498,7 @@ int cg_setup(const Geom& g, double mass, const void* U, const void* b, void* x, 
 
 int cg_plain(const Geom& g, double mass, const void* U, const void* b, void* x, const wd_cg_params* p,
              wd_cg_result* res, void* ws, hipStream_t s, std::chrono::steady_clock::time_point t0) {
-  const CgWorkspace w = layout_cg(ws, g, WD_F64, p->history_len);
+  const CgWorkspace w = layout_cg(ws, g, WD_F64, p->history_len, ring_length(p));
   int rc = cg_setup(g, mass, U, b, x, p, w, 0, 0.0, w.r64, s);
   if (rc) return rc;
   launch_convert(g, w.r64, w.p64, G_ALWAYS, w.st, s);
@@ -545,7 +564,7 @@ int cg_plain(const Geom& g, double mass, const void* U, const void* b, void* x, 
   if ((rc = copy_history(w, p, s, st.iter))) return rc;
   HIP_TRY(hipStreamSynchronize(s));
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  if (res) clock_read(clk, enqueued, res->kernel_seconds);
+  if (res) clock_read(clk, enqueued, 3, res->kernel_seconds);
   int code;
   if (st.status < 0) code = status_to_code(st.status);
   else if (st.rho_true <= st.stop2) code = WD_OK;
@@ -563,7 +582,7 @@ int cg_mixed(const Geom& g, double mass, const void* U, const void* b, void* x, 
   const bool refine = p->scheme == WD_ITERATIVE_REFINEMENT;
   // refinement: no periodic recomputation, only after each inner solve
   const int interval = refine ? (1 << 30) : (p->reliable_interval > 0 ? p->reliable_interval : 50);
-  const CgWorkspace w = layout_cg(ws, g, P, p->history_len);
+  const CgWorkspace w = layout_cg(ws, g, P, p->history_len, ring_length(p));
   // Besides every `interval` iterations, recompute the residual whenever the
   // iterated residual has fallen by `delta` since the last update, so that
   // the low-precision drift (~ unit roundoff x the residual at the last
@@ -587,8 +606,10 @@ int cg_mixed(const Geom& g, double mass, const void* U, const void* b, void* x, 
   }
   if (rows2) launch_pack_gauge_rows2(g, U, P, w.Ulow, s);
   else launch_pack_gauge(g, U, P, w.Ulow, s);
-  launch_zero(g, w.xh, G_ALWAYS, w.st, s);
-  launch_convert(g, w.rh, w.ph, G_ALWAYS, w.st, s);
+  // p_0 = r_0 in ring slot 0; fold the ring into x before it overflows: at
+  // most kSlotEvery iterations pass between two checks
+  launch_convert(g, w.rh, w.ring.at(0), G_ALWAYS, w.st, s);
+  launch_set_ring(w.st, w.alpha_hist, w.ring.len - (kSlotEvery - 1), w.ring.len, s);
   HIP_TRY(hipGetLastError());
 
   KernelClock* clk = nullptr;
@@ -597,23 +618,27 @@ int cg_mixed(const Geom& g, double mass, const void* U, const void* b, void* x, 
   SolverState st{};
   st.stop2 = 1;
   int enqueued = 0;
-  const int slot_every = 5;   // a reliable-update slot after every 5th enqueued iteration
   for (;;) {
     while (poll.pending < 2) {
       int n = next_chunk(st, enqueued, p->max_iter);
       if (n <= 0) break;
       for (int k = 0; k < n; ++k) {
         const int i = enqueued + k;
-        launch_wilson_packed(g, P, w.Ulow, w.ph, w.th, mass, 0, G_ITER, F_ALPHA, w.st, w.partials, s,
-                             clock_at(clk, 0, i), rows2);
-        launch_cg_update(g, P, w.Ulow, w.th, w.rh, w.ph, w.xh, mass, w.st, w.partials, s, clock_at(clk, 1, i),
-                         rows2);
-        if ((enqueued + k + 1) % slot_every == 0) {
-          launch_accumulate(g, w.x64, w.xh, G_RELIABLE, w.st, s);
+        // t = D p (p = ring slot npend), alpha; r -= alpha D^+ t, beta
+        launch_wilson_packed(g, P, w.Ulow, w.rh, w.th, mass, 0, G_ITER, F_ALPHA_RING, w.st, w.partials, s,
+                             clock_at(clk, 0, i), rows2, &w.ring);
+        launch_r_update(g, P, w.Ulow, w.th, w.rh, mass, w.st, w.partials, s, clock_at(clk, 1, i), rows2);
+        if ((enqueued + k + 1) % kSlotEvery == 0) {
+          // ring nearly full: x += sum alpha_j p_j without a residual recomputation
+          launch_accumulate_ring(g, w.x64, w.ring, G_FLUSH, w.st, s);
+          launch_ring_reset(w.st, s);
+          // reliable update: x += sum alpha_j p_j, r = b' - D^+ D x in FP64
+          launch_accumulate_ring(g, w.x64, w.ring, G_RELIABLE, w.st, s);
           launch_wilson_packed(g, P_F64, w.U64, w.x64, w.t64, mass, 0, G_RELIABLE, F_NONE, w.st, w.partials, s);
           launch_residual(g, w.U64, w.t64, w.b64, w.rh, mass, G_RELIABLE, F_RELIABLE, w.st, w.partials, s);
         }
-        launch_p_update(g, w.rh, w.ph, w.st, s, clock_at(clk, 2, i));
+        // next p into ring slot npend
+        launch_p_update_ring(g, w.rh, w.ring, w.st, s, clock_at(clk, 2, i));
       }
       enqueued += n;
       HIP_TRY(hipGetLastError());
@@ -627,8 +652,9 @@ int cg_mixed(const Geom& g, double mass, const void* U, const void* b, void* x, 
   if ((rc = poll.drain(&st))) return rc;
   const double iter_rel = std::sqrt(st.rho / (st.bnorm2 > 0 ? st.bnorm2 : 1.0));
   if (st.status != 1) {
-    // max_iter reached (or an error): flush x-hat and measure the true residual
-    launch_accumulate(g, w.x64, w.xh, G_FINAL, w.st, s);
+    // max_iter reached (or an error): fold the pending p vectors into x and
+    // measure the true residual
+    launch_accumulate_ring(g, w.x64, w.ring, G_FINAL, w.st, s);
     launch_wilson_packed(g, P_F64, w.U64, w.x64, w.t64, mass, 0, G_FINAL, F_NONE, w.st, w.partials, s);
     launch_residual(g, w.U64, w.t64, w.b64, w.rh, mass, G_FINAL, F_TRUE, w.st, w.partials, s);
     if ((rc = poll.post(w.st))) return rc;
@@ -640,7 +666,7 @@ int cg_mixed(const Geom& g, double mass, const void* U, const void* b, void* x, 
   HIP_TRY(hipStreamSynchronize(s));
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (res) {
-    clock_read(clk, enqueued, res->kernel_seconds);
+    clock_read(clk, enqueued, 3, res->kernel_seconds);
     res->two_row_links = rows2;
   }
   int code;

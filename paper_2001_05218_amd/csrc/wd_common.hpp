@@ -232,6 +232,7 @@ template <int P> struct PackedSpinor;
 
 template <> struct PackedSpinor<P_F64> {
   using Real = double;
+  static constexpr bool kFence = false;
   double2* data;
   float* scale;  // unused
   __device__ __forceinline__ void load(int s, Real v[24]) const {
@@ -250,6 +251,7 @@ template <> struct PackedSpinor<P_F64> {
 
 template <> struct PackedSpinor<P_F32> {
   using Real = float;
+  static constexpr bool kFence = false;
   float4* data;
   float* scale;
   __device__ __forceinline__ void load(int s, Real v[24]) const {
@@ -268,6 +270,7 @@ template <> struct PackedSpinor<P_F32> {
 
 template <> struct PackedSpinor<P_BF16> {
   using Real = float;
+  static constexpr bool kFence = false;
   uint4* data;
   float* scale;
   static __device__ __forceinline__ void unpack(const uint4 d[3], float, Real v[24]) {
@@ -288,19 +291,32 @@ template <> struct PackedSpinor<P_BF16> {
     for (int w = 0; w < 3; ++w) d[w] = data[word_index(s, 3, w)];
     unpack(d, 1.0f, v);
   }
-  __device__ __forceinline__ void store(int s, const Real v[24]) const {
+  // Rounded raw words of a spinor (the scale is always 1 for BF16).
+  static __device__ __forceinline__ void pack(const Real v[24], uint4 d[3], float& sc) {
 #pragma unroll
     for (int w = 0; w < 3; ++w) {
       uint32_t u[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) u[k] = pack_bf16x2(v[8 * w + 2 * k], v[8 * w + 2 * k + 1]);
-      data[word_index(s, 3, w)] = make_uint4(u[0], u[1], u[2], u[3]);
+      d[w] = make_uint4(u[0], u[1], u[2], u[3]);
     }
+    sc = 1.0f;
+  }
+  __device__ __forceinline__ void store_raw(int s, const uint4 d[3], float) const {
+#pragma unroll
+    for (int w = 0; w < 3; ++w) data[word_index(s, 3, w)] = d[w];
+  }
+  __device__ __forceinline__ void store(int s, const Real v[24]) const {
+    uint4 d[3];
+    float sc;
+    pack(v, d, sc);
+    store_raw(s, d, sc);
   }
 };
 
 template <> struct PackedSpinor<P_F16> {
   using Real = float;
+  static constexpr bool kFence = false;
   uint4* data;
   float* scale;   // per-site magnitude: stored value = v / scale, |stored| <= 1
   static __device__ __forceinline__ void unpack(const uint4 d[3], float sc, Real v[24]) {
@@ -321,26 +337,39 @@ template <> struct PackedSpinor<P_F16> {
     for (int w = 0; w < 3; ++w) d[w] = data[word_index(s, 3, w)];
     unpack(d, scale[s], v);
   }
-  __device__ __forceinline__ void store(int s, const Real v[24]) const {
+  // Rounded raw words and scale of a spinor.
+  static __device__ __forceinline__ void pack(const Real v[24], uint4 d[3], float& sc) {
     float m = 0.f;
 #pragma unroll
     for (int i = 0; i < 24; ++i) m = fmaxf(m, fabsf(v[i]));
     const float inv = (m > 0.f) ? 1.0f / m : 0.f;
-    scale[s] = m;
+    sc = m;
 #pragma unroll
     for (int w = 0; w < 3; ++w) {
       uint32_t u[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         u[k] = pack_f16x2(v[8 * w + 2 * k] * inv, v[8 * w + 2 * k + 1] * inv);
-      data[word_index(s, 3, w)] = make_uint4(u[0], u[1], u[2], u[3]);
+      d[w] = make_uint4(u[0], u[1], u[2], u[3]);
     }
+  }
+  __device__ __forceinline__ void store_raw(int s, const uint4 d[3], float sc) const {
+    scale[s] = sc;
+#pragma unroll
+    for (int w = 0; w < 3; ++w) data[word_index(s, 3, w)] = d[w];
+  }
+  __device__ __forceinline__ void store(int s, const Real v[24]) const {
+    uint4 d[3];
+    float sc;
+    pack(v, d, sc);
+    store_raw(s, d, sc);
   }
 };
 
 // Canonical boundary layout: (Lt, Lz, Ly, Lx, 4, 3) complex128, AoS.
 struct CanonSpinor {
   using Real = double;
+  static constexpr bool kFence = false;
   double2* data;
   __device__ __forceinline__ void load(int s, Real v[24]) const {
     const double2* p = data + (size_t)s * 12;

@@ -139,6 +139,14 @@ __device__ __forceinline__ void hop_dir(const Gauge& U, const Src& in, int s, co
   project<MU, SB>(psi, h);
   su3_mul_half<true>(u, h, w);
   reconstruct_add<MU, SB>(acc, w);
+  // Sources that read LDS: finish this direction's arithmetic here. Without
+  // the empty asm the optimiser sinks every hop's arithmetic to the final
+  // sum, which keeps all eight neighbours' loaded values live at once.
+  if constexpr (Src::kFence) {
+#pragma unroll
+    for (int i = 0; i < 24; ++i) asm volatile("" : "+v"(acc[i]));
+    __builtin_amdgcn_sched_barrier(0);
+  }
 }
 
 // out = (m + 4) psi(x) - 1/2 sum_mu hops, arithmetic in R.

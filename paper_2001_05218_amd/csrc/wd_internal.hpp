@@ -26,17 +26,19 @@ struct SolverState {
   double su3_dev;    // largest deviation of a link from SU(3) (F_SU3MAX)
   double delta2;     // mixed: also update once rho <= delta2 * rho_update
   int iter;          // inner iterations completed
-  int status;        // 0 running, 1 converged, -3 breakdown, -4 NaN/Inf
+  int status;        // 0 running, 1 converged, -3 breakdown, -4 NaN/Inf, -5 ring overflow
   int inner_done;    // mixed: inner residual reached the target; update pending
   int last_update;   // iteration of the last reliable update
   int interval;      // reliable-update interval (mixed)
   int rel_updates;   // reliable updates performed
   int restart_on_update;  // refinement: every FP64 recomputation restarts the Krylov space (beta = 0)
   int hist_len;      // capacity of hist
-  int pad0;
-  unsigned int pad2;
-  unsigned int pad1;
+  int npend;         // mixed: p vectors in the ring whose x update is still pending
+  int pcur;          // mixed: ring slot of the current search direction p
+  int flush_at;      // mixed: fold the ring into x once npend reaches this (0: never)
+  int ring_len;      // mixed: slots in the ring (npend never exceeds it; -5 status if it would)
   double* hist;      // per-iteration relative residual (device, in the workspace)
+  double* alpha_hist;  // mixed: alpha of the p in each ring slot (device, in the workspace)
 };
 
 // When a kernel runs. Decided identically by every workgroup from the state,
@@ -48,6 +50,7 @@ enum Gate : int {
   G_RELIABLE = 2, // reliable-update slot: status == 0 and (pending, interval reached, or
                   //   residual reduced by delta since the last update)
   G_FINAL = 3,    // final FP64 recomputation: unconditional
+  G_FLUSH = 4,    // mixed: status == 0 and the ring of pending p vectors is nearly full
 };
 
 // What the last workgroup does with the reduced sum.
@@ -61,6 +64,7 @@ enum Fin : int {
                    //   (beta = 0, a restart, if the true residual exceeds twice the iterated one)
   F_TRUE = 6,      // rho_true = sum (final recomputation)
   F_SU3MAX = 7,    // su3_dev = max of the partials (the finalize takes a maximum, not a sum)
+  F_ALPHA_RING = 8,  // F_ALPHA, then alpha_hist[npend] = alpha, pcur = npend, npend += 1
 };
 
 // Optional pair of events recorded on the launch stream right before and
@@ -74,6 +78,25 @@ struct SpinorBuf {
   void* data;
   float* scale;   // FP16 storage only
   int prec;
+};
+
+// Ring of search directions for the deferred solution update of the mixed
+// solver: slot j holds a packed spinor at data + j * stride (FP16 scales at
+// scale + j * scale_stride). A null `data` means "no ring".
+struct RingBuf {
+  char* data;
+  char* scale;
+  long long stride;
+  long long scale_stride;
+  int prec;
+  int len;
+  __host__ __device__ SpinorBuf at(int j) const {
+    SpinorBuf b;
+    b.data = data + j * stride;
+    b.scale = scale ? reinterpret_cast<float*>(scale + j * scale_stride) : nullptr;
+    b.prec = prec;
+    return b;
+  }
 };
 
 // ---- launchers (wd_kernels.hip). All asynchronous on `stream`.
@@ -94,9 +117,10 @@ void launch_zero(const Geom& g, SpinorBuf v, int gate, SolverState* st, hipStrea
 void launch_wilson_canonical(const Geom& g, const void* U, const void* in, void* out, double mass, int dagger,
                              hipStream_t s);
 // out = D in / D^+ in on packed fields of one precision; optional reduction of ||out||^2.
+// With `ring`, the input is ring slot st->npend instead of `in` (mixed solver).
 void launch_wilson_packed(const Geom& g, int prec, const void* U, SpinorBuf in, SpinorBuf out, double mass,
                           int dagger, int gate, int fin, SolverState* st, double* partials, hipStream_t s,
-                          const EventPair* ev = nullptr, int rows2 = 0);
+                          const EventPair* ev = nullptr, int rows2 = 0, const RingBuf* ring = nullptr);
 // Two-row (12-real) 16-bit gauge copy (BF16 or FP16), tiled lattices; the
 // tiled 16-bit kernels rebuild row 2 from unitarity (rows2 = 1).
 void launch_pack_gauge_rows2(const Geom& g, const void* U_c128, int prec, void* out, hipStream_t s);
@@ -112,6 +136,21 @@ void launch_residual(const Geom& g, const void* U64, SpinorBuf t64, SpinorBuf b6
 // p = r + beta p
 void launch_p_update(const Geom& g, SpinorBuf r, SpinorBuf p, SolverState* st, hipStream_t s,
                      const EventPair* ev = nullptr);
+// Mixed solver with a ring of search directions (the deferred x update):
+//   t = D ring[npend] (+ ||t||^2 -> F_ALPHA_RING) is launch_wilson_packed with `ring`;
+//   q = D^+ t (never stored); r -= alpha q; ||r||^2 -> F_BETA.
+void launch_r_update(const Geom& g, int prec, const void* U, SpinorBuf t, SpinorBuf r, double mass, SolverState* st,
+                     double* partials, hipStream_t s, const EventPair* ev = nullptr, int rows2 = 0);
+//   ring[npend] = r + beta ring[pcur] (in place when the two slots coincide).
+void launch_p_update_ring(const Geom& g, SpinorBuf r, const RingBuf& ring, SolverState* st, hipStream_t s,
+                          const EventPair* ev = nullptr);
+//   x(FP64) += sum_{j < npend} alpha_hist[j] ring[j], accumulated in FP64.
+void launch_accumulate_ring(const Geom& g, SpinorBuf x64, const RingBuf& ring, int gate, SolverState* st,
+                            hipStream_t s);
+//   npend = 0 when G_FLUSH is open (after launch_accumulate_ring with G_FLUSH).
+void launch_ring_reset(SolverState* st, hipStream_t s);
+//   alpha_hist, flush_at and ring_len of the state.
+void launch_set_ring(SolverState* st, double* alpha_hist, int flush_at, int ring_len, hipStream_t s);
 // x(FP64) += xhat; xhat = 0
 void launch_accumulate(const Geom& g, SpinorBuf x64, SpinorBuf xhat, int gate, SolverState* st, hipStream_t s);
 // ||v||^2 -> fin

@@ -48,10 +48,23 @@ __device__ void finalize(SolverState* st, int fin, double sum) {
       else if (sum <= st->stop2) st->status = 1;
       break;
     case F_ALPHA:
+    case F_ALPHA_RING:
       st->tnorm = sum;
       if (!finite_d(sum)) st->status = -4;
       else if (sum <= 0.0) st->status = -3;
       else st->alpha = st->rho / sum;
+      if (fin == F_ALPHA_RING) {
+        // the p just applied (ring slot npend) joins the pending x update.
+        // The host folds the ring often enough that npend < ring_len here;
+        // if not, D and the p update skipped their ring access: stop.
+        if (st->npend >= st->ring_len) {
+          st->status = -5;
+        } else {
+          st->alpha_hist[st->npend] = st->alpha;
+          st->pcur = st->npend;
+          st->npend += 1;
+        }
+      }
       break;
     case F_BETA: {
       st->rho_prev = st->rho;
@@ -76,6 +89,7 @@ __device__ void finalize(SolverState* st, int fin, double sum) {
       st->rel_updates += 1;
       st->last_update = st->iter;
       st->inner_done = 0;
+      st->npend = 0;   // the pending x update went into the accumulation before this
       if (!finite_d(sum)) st->status = -4;
       else if (sum <= st->stop2) st->status = 1;
       else {
@@ -115,6 +129,7 @@ __device__ __forceinline__ bool gate_open(const SolverState* st, int gate) {
   if (gate == G_ALWAYS || gate == G_FINAL) return true;
   const int status = st->status;
   if (gate == G_ITER) return status == 0 && st->inner_done == 0;
+  if (gate == G_FLUSH) return status == 0 && st->flush_at > 0 && st->npend >= st->flush_at;
   // G_RELIABLE
   return status == 0 && (st->inner_done != 0 || st->iter - st->last_update >= st->interval ||
                          st->rho <= st->delta2 * st->rho_update);
@@ -128,8 +143,19 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(const double* __restrict
   if (!gate_open(st, gate)) return;
   __shared__ double wsum[kFinBlock / 64];
   const bool use_max = (fin == F_SU3MAX);
+  // eight loads in flight per thread before any add (the partials were just
+  // written by other XCDs, so each load is a full memory round trip)
   double v = 0.0;
-  for (int i = threadIdx.x; i < n; i += kFinBlock) v = use_max ? fmax(v, partials[i]) : v + partials[i];
+  for (int base = 0; base < n; base += 8 * kFinBlock) {
+    double a[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int i = base + k * kFinBlock + threadIdx.x;
+      a[k] = i < n ? partials[i] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v = use_max ? fmax(v, a[k]) : v + a[k];
+  }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     const double o = __shfl_xor(v, off, 64);
@@ -319,18 +345,39 @@ __global__ __launch_bounds__(kBlock) void k_wilson_canonical(Geom g, CanonGauge 
   out.store(s, o);
 }
 
-template <int P, bool DAG>
+// The stencil at site s of workgroup tile T: from the LDS-staged tile when
+// TILE (FP64 / FP32 on the tiled order; every thread of the workgroup must
+// get here), else straight from memory.
+template <int P, bool DAG, bool TILE>
+__device__ __forceinline__ void stencil_at(const Geom& g, const void* U, const SpinorBuf& in, int T, int s,
+                                           typename PackedSpinor<P>::Real diag,
+                                           typename PackedSpinor<P>::Real o[24]) {
+  const Nbrs nb = neighbours(g, s);
+  if constexpr (TILE) {
+    __shared__ typename TileWord<P>::T lds[TileWord<P>::n * kTileSites];
+    const TileSrc<P> src = stage_own_tile<P>(in, T, lds);
+    wilson_site<DAG>(gauge_of<P>(U), src, s, nb, diag, o);
+  } else {
+    wilson_site<DAG>(gauge_of<P>(U), spinor_of<P>(in), s, nb, diag, o);
+  }
+}
+
+template <int P, bool DAG, bool TILE>
 __global__ __launch_bounds__(kBlock) void k_wilson_packed(Geom g, const void* U, SpinorBuf in, SpinorBuf out,
                                                           double diag, int gate, int fin, SolverState* st,
-                                                          double* partials) {
+                                                          double* partials, RingBuf ring) {
   if (!gate_open(st, gate)) return;
+  if (ring.data) {
+    if (st->npend >= ring.len) return;   // never with the host's fold cadence
+    in = ring.at(st->npend);
+  }
   using R = typename PackedSpinor<P>::Real;
-  const int s = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const int T = xcd_tile(blockIdx.x, gridDim.x);
+  const int s = T * kBlock + threadIdx.x;
   double n2 = 0.0;
-  if (s < g.V) {
-    const Nbrs nb = neighbours(g, s);
+  if (TILE || s < g.V) {
     R o[24];
-    wilson_site<DAG>(gauge_of<P>(U), spinor_of<P>(in), s, nb, (R)diag, o);
+    stencil_at<P, DAG, TILE>(g, U, in, T, s, (R)diag, o);
     spinor_of<P>(out).store(s, o);
     if (fin != F_NONE) {
 #pragma unroll
@@ -348,8 +395,12 @@ __global__ __launch_bounds__(kBlock) void k_wilson_packed(Geom g, const void* U,
 template <int P, bool C12, bool DAG>
 __global__ __launch_bounds__(kBlock) WD_TILED_OCCUPANCY void k_wilson_tiled(Geom g, const void* U, SpinorBuf in, SpinorBuf out,
                                                          double diag, int gate, int fin, SolverState* st,
-                                                         double* partials) {
+                                                         double* partials, RingBuf ring) {
   if (!gate_open(st, gate)) return;
+  if (ring.data) {
+    if (st->npend >= ring.len) return;   // never with the host's fold cadence
+    in = ring.at(st->npend);
+  }
   __shared__ TileLds<P> lds;
   const int T = xcd_tile(blockIdx.x, gridDim.x);
   uint32_t lk[8][9];
@@ -366,8 +417,10 @@ __global__ __launch_bounds__(kBlock) WD_TILED_OCCUPANCY void k_wilson_tiled(Geom
   }
 }
 
-// CG update with the LDS-staged D^+ (16-bit storage, tiled order).
-template <int P, bool C12>
+// CG update with the LDS-staged D^+ (16-bit storage, tiled order). With XP
+// the kernel also does x += alpha p; without it (the fused loop) that update
+// is left to the next iteration's p update, which reads p anyway.
+template <int P, bool C12, bool XP>
 __global__ __launch_bounds__(kBlock) WD_TILED_OCCUPANCY void k_cg_update_tiled(Geom g, const void* U, SpinorBuf t, SpinorBuf r,
                                                             SpinorBuf p, SpinorBuf x, double diag, SolverState* st,
                                                             double* partials) {
@@ -381,18 +434,20 @@ __global__ __launch_bounds__(kBlock) WD_TILED_OCCUPANCY void k_cg_update_tiled(G
   tile_wilson<P, C12, true>(lds, lk, (float)diag, q);
   const int s = T * kTileSites + threadIdx.x;
   const float a = (float)st->alpha;
-  float rv[24], pv[24], xv[24];
+  float rv[24];
   const auto rs = spinor_of<P>(r);
   rs.load(s, rv);
-  spinor_of<P>(p).load(s, pv);
-  spinor_of<P_F32>(x).load(s, xv);
+  if constexpr (XP) {
+    float pv[24], xv[24];
+    spinor_of<P>(p).load(s, pv);
+    spinor_of<P_F32>(x).load(s, xv);
 #pragma unroll
-  for (int i = 0; i < 24; ++i) {
-    rv[i] = fmaf(-a, q[i], rv[i]);
-    xv[i] = fmaf(a, pv[i], xv[i]);
+    for (int i = 0; i < 24; ++i) xv[i] = fmaf(a, pv[i], xv[i]);
+    spinor_of<P_F32>(x).store(s, xv);
   }
+#pragma unroll
+  for (int i = 0; i < 24; ++i) rv[i] = fmaf(-a, q[i], rv[i]);
   rs.store(s, rv);
-  spinor_of<P_F32>(x).store(s, xv);
   rs.load(s, rv);   // the norm of what the next iteration reads
   double n2 = 0.0;
 #pragma unroll
@@ -401,35 +456,37 @@ __global__ __launch_bounds__(kBlock) WD_TILED_OCCUPANCY void k_cg_update_tiled(G
 }
 
 // q = D^+ t at site s; r -= alpha q; x += alpha p; reduce ||r||^2 (of the stored r).
-template <int P, int PX>
+template <int P, int PX, bool TILE, bool XP>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_cg_update(Geom g, const void* U, SpinorBuf t, SpinorBuf r, SpinorBuf p,
                                                       SpinorBuf x, double diag, SolverState* st, double* partials) {
   if (!gate_open(st, G_ITER)) return;
   using R = typename PackedSpinor<P>::Real;
   using RX = typename PackedSpinor<PX>::Real;
-  const int s = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const int T = xcd_tile(blockIdx.x, gridDim.x);
+  const int s = T * kBlock + threadIdx.x;
   const double alpha = st->alpha;
   double n2 = 0.0;
-  if (s < g.V) {
-    const Nbrs nb = neighbours(g, s);
+  if (TILE || s < g.V) {
     R q[24];
-    wilson_site<true>(gauge_of<P>(U), spinor_of<P>(t), s, nb, (R)diag, q);
+    stencil_at<P, true, TILE>(g, U, t, T, s, (R)diag, q);
     // the epilogue's loads are not hoisted into the stencil (register pressure)
     __builtin_amdgcn_sched_barrier(0);
-    R rv[24], pv[24];
-    RX xv[24];
+    R rv[24];
     const auto rs = spinor_of<P>(r);
     rs.load(s, rv);
-    spinor_of<P>(p).load(s, pv);
-    spinor_of<PX>(x).load(s, xv);
+    if constexpr (XP) {
+      R pv[24];
+      RX xv[24];
+      spinor_of<P>(p).load(s, pv);
+      spinor_of<PX>(x).load(s, xv);
+#pragma unroll
+      for (int i = 0; i < 24; ++i) xv[i] = fma((RX)alpha, (RX)pv[i], xv[i]);
+      spinor_of<PX>(x).store(s, xv);
+    }
     const R a = (R)alpha;
 #pragma unroll
-    for (int i = 0; i < 24; ++i) {
-      rv[i] = fma(-a, q[i], rv[i]);
-      xv[i] = fma((RX)alpha, (RX)pv[i], xv[i]);
-    }
+    for (int i = 0; i < 24; ++i) rv[i] = fma(-a, q[i], rv[i]);
     rs.store(s, rv);
-    spinor_of<PX>(x).store(s, xv);
     if constexpr (P == P_F64 || P == P_F32) {
 #pragma unroll
       for (int i = 0; i < 24; ++i) n2 += (double)rv[i] * (double)rv[i];
@@ -444,17 +501,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
 }
 
 // out = low(b - D^+ t) in FP64 arithmetic (t, b and links FP64); reduce the FP64 norm.
-template <int PO>
+template <int PO, bool TILE>
 __global__ __launch_bounds__(kBlock) void k_residual(Geom g, const void* U64, SpinorBuf t64, SpinorBuf b64,
                                                      SpinorBuf out, double diag, int gate, int fin, SolverState* st,
                                                      double* partials) {
   if (!gate_open(st, gate)) return;
-  const int s = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  const int T = xcd_tile(blockIdx.x, gridDim.x);
+  const int s = T * kBlock + threadIdx.x;
   double n2 = 0.0;
-  if (s < g.V) {
-    const Nbrs nb = neighbours(g, s);
+  if (TILE || s < g.V) {
     double q[24], b[24];
-    wilson_site<true>(gauge_of<P_F64>(U64), spinor_of<P_F64>(t64), s, nb, diag, q);
+    stencil_at<P_F64, true, TILE>(g, U64, t64, T, s, diag, q);
     spinor_of<P_F64>(b64).load(s, b);
     typename PackedSpinor<PO>::Real o[24];
 #pragma unroll
@@ -500,6 +557,58 @@ __global__ __launch_bounds__(kBlock) void k_accumulate(Geom g, SpinorBuf x64, Sp
   }
   spinor_of<P_F64>(x64).store(s, xv);
   spinor_of<PX>(xhat).store(s, hv);
+}
+
+// Mixed solver, deferred x update: ring[npend] = r + beta ring[pcur].
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_p_update_ring(Geom g, SpinorBuf r, RingBuf ring, const SolverState* st) {
+  if (!gate_open(st, G_ITER)) return;
+  using R = typename PackedSpinor<P>::Real;
+  const int s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= g.V || st->npend >= ring.len) return;   // the latter never with the host's fold cadence
+  const R beta = (R)st->beta;
+  R rv[24], pv[24];
+  spinor_of<P>(r).load(s, rv);
+  spinor_of<P>(ring.at(st->pcur)).load(s, pv);
+#pragma unroll
+  for (int i = 0; i < 24; ++i) pv[i] = fma(beta, pv[i], rv[i]);
+  spinor_of<P>(ring.at(st->npend)).store(s, pv);
+}
+
+// x(FP64) += sum_{j < npend} alpha_j p_j over the ring, in FP64 arithmetic.
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_accumulate_ring(Geom g, SpinorBuf x64, RingBuf ring, int gate,
+                                                            const SolverState* st) {
+  if (!gate_open(st, gate)) return;
+  const int s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= g.V) return;
+  const int n = st->npend;
+  if (n == 0) return;
+  double xv[24];
+  spinor_of<P_F64>(x64).load(s, xv);
+  for (int j = 0; j < n; ++j) {
+    typename PackedSpinor<P>::Real pv[24];
+    spinor_of<P>(ring.at(j)).load(s, pv);
+    const double a = st->alpha_hist[j];
+#pragma unroll
+    for (int i = 0; i < 24; ++i) xv[i] = fma(a, (double)pv[i], xv[i]);
+  }
+  spinor_of<P_F64>(x64).store(s, xv);
+}
+
+__global__ void k_ring_reset(SolverState* st) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (!gate_open(st, G_FLUSH)) return;
+  st->npend = 0;
+}
+
+__global__ void k_set_ring(SolverState* st, double* alpha_hist, int flush_at, int ring_len) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  st->alpha_hist = alpha_hist;
+  st->flush_at = flush_at;
+  st->ring_len = ring_len;
+  st->npend = 0;
+  st->pcur = 0;
 }
 
 template <int P>
@@ -718,33 +827,42 @@ static void launch(void (*kernel)(KArgs...), const Geom& g, hipStream_t s, const
 template <int P>
 static void wilson_packed_p(const Geom& g, const void* U, SpinorBuf in, SpinorBuf out, double mass, int dagger,
                             int gate, int fin, SolverState* st, double* partials, hipStream_t s,
-                            const EventPair* ev, int rows2) {
+                            const EventPair* ev, int rows2, RingBuf ring) {
   const double d = mass + 4.0;
   bool done = false;
   if constexpr (P == P_BF16 || P == P_F16) {
     if (g.tiled) {
-      if (rows2 && dagger) launch(k_wilson_tiled<P, true, true>, g, s, ev, g, U, in, out, d, gate, fin, st, partials);
-      else if (rows2) launch(k_wilson_tiled<P, true, false>, g, s, ev, g, U, in, out, d, gate, fin, st, partials);
-      else if (dagger) launch(k_wilson_tiled<P, false, true>, g, s, ev, g, U, in, out, d, gate, fin, st, partials);
-      else launch(k_wilson_tiled<P, false, false>, g, s, ev, g, U, in, out, d, gate, fin, st, partials);
+      if (rows2 && dagger) launch(k_wilson_tiled<P, true, true>, g, s, ev, g, U, in, out, d, gate, fin, st, partials, ring);
+      else if (rows2) launch(k_wilson_tiled<P, true, false>, g, s, ev, g, U, in, out, d, gate, fin, st, partials, ring);
+      else if (dagger) launch(k_wilson_tiled<P, false, true>, g, s, ev, g, U, in, out, d, gate, fin, st, partials, ring);
+      else launch(k_wilson_tiled<P, false, false>, g, s, ev, g, U, in, out, d, gate, fin, st, partials, ring);
+      done = true;
+    }
+  }
+  if constexpr (P == P_F64 || P == P_F32) {
+    if (g.tiled) {
+      if (dagger) launch(k_wilson_packed<P, true, true>, g, s, ev, g, U, in, out, d, gate, fin, st, partials, ring);
+      else launch(k_wilson_packed<P, false, true>, g, s, ev, g, U, in, out, d, gate, fin, st, partials, ring);
       done = true;
     }
   }
   if (!done) {
-    if (dagger) launch(k_wilson_packed<P, true>, g, s, ev, g, U, in, out, d, gate, fin, st, partials);
-    else launch(k_wilson_packed<P, false>, g, s, ev, g, U, in, out, d, gate, fin, st, partials);
+    if (dagger) launch(k_wilson_packed<P, true, false>, g, s, ev, g, U, in, out, d, gate, fin, st, partials, ring);
+    else launch(k_wilson_packed<P, false, false>, g, s, ev, g, U, in, out, d, gate, fin, st, partials, ring);
   }
   if (fin != F_NONE) launch_finalize(g, partials, st, fin, gate, s);
 }
 
 void launch_wilson_packed(const Geom& g, int prec, const void* U, SpinorBuf in, SpinorBuf out, double mass,
                           int dagger, int gate, int fin, SolverState* st, double* partials, hipStream_t s,
-                          const EventPair* ev, int rows2) {
+                          const EventPair* ev, int rows2, const RingBuf* ring) {
+  RingBuf rg{};
+  if (ring) rg = *ring;
   switch (prec) {
-    case P_F64: wilson_packed_p<P_F64>(g, U, in, out, mass, dagger, gate, fin, st, partials, s, ev, 0); break;
-    case P_F32: wilson_packed_p<P_F32>(g, U, in, out, mass, dagger, gate, fin, st, partials, s, ev, 0); break;
-    case P_BF16: wilson_packed_p<P_BF16>(g, U, in, out, mass, dagger, gate, fin, st, partials, s, ev, rows2); break;
-    default: wilson_packed_p<P_F16>(g, U, in, out, mass, dagger, gate, fin, st, partials, s, ev, rows2); break;
+    case P_F64: wilson_packed_p<P_F64>(g, U, in, out, mass, dagger, gate, fin, st, partials, s, ev, 0, rg); break;
+    case P_F32: wilson_packed_p<P_F32>(g, U, in, out, mass, dagger, gate, fin, st, partials, s, ev, 0, rg); break;
+    case P_BF16: wilson_packed_p<P_BF16>(g, U, in, out, mass, dagger, gate, fin, st, partials, s, ev, rows2, rg); break;
+    default: wilson_packed_p<P_F16>(g, U, in, out, mass, dagger, gate, fin, st, partials, s, ev, rows2, rg); break;
   }
 }
 
@@ -763,30 +881,103 @@ void launch_cg_update(const Geom& g, int prec, const void* U, SpinorBuf t, Spino
                       double mass, SolverState* st, double* partials, hipStream_t s, const EventPair* ev, int rows2) {
   const double diag = mass + 4.0;
   switch (prec) {
-    case P_F64: launch(k_cg_update<P_F64, P_F64>, g, s, ev, g, U, t, r, p, x, diag, st, partials); break;
-    case P_F32: launch(k_cg_update<P_F32, P_F32>, g, s, ev, g, U, t, r, p, x, diag, st, partials); break;
+    case P_F64:
+      if (g.tiled) launch(k_cg_update<P_F64, P_F64, true, true>, g, s, ev, g, U, t, r, p, x, diag, st, partials);
+      else launch(k_cg_update<P_F64, P_F64, false, true>, g, s, ev, g, U, t, r, p, x, diag, st, partials);
+      break;
+    case P_F32:
+      if (g.tiled) launch(k_cg_update<P_F32, P_F32, true, true>, g, s, ev, g, U, t, r, p, x, diag, st, partials);
+      else launch(k_cg_update<P_F32, P_F32, false, true>, g, s, ev, g, U, t, r, p, x, diag, st, partials);
+      break;
     case P_BF16:
-      if (g.tiled && rows2) launch(k_cg_update_tiled<P_BF16, true>, g, s, ev, g, U, t, r, p, x, diag, st, partials);
-      else if (g.tiled) launch(k_cg_update_tiled<P_BF16, false>, g, s, ev, g, U, t, r, p, x, diag, st, partials);
-      else launch(k_cg_update<P_BF16, P_F32>, g, s, ev, g, U, t, r, p, x, diag, st, partials);
+      if (g.tiled && rows2) launch(k_cg_update_tiled<P_BF16, true, true>, g, s, ev, g, U, t, r, p, x, diag, st, partials);
+      else if (g.tiled) launch(k_cg_update_tiled<P_BF16, false, true>, g, s, ev, g, U, t, r, p, x, diag, st, partials);
+      else launch(k_cg_update<P_BF16, P_F32, false, true>, g, s, ev, g, U, t, r, p, x, diag, st, partials);
       break;
     default:
-      if (g.tiled && rows2) launch(k_cg_update_tiled<P_F16, true>, g, s, ev, g, U, t, r, p, x, diag, st, partials);
-      else if (g.tiled) launch(k_cg_update_tiled<P_F16, false>, g, s, ev, g, U, t, r, p, x, diag, st, partials);
-      else launch(k_cg_update<P_F16, P_F32>, g, s, ev, g, U, t, r, p, x, diag, st, partials);
+      if (g.tiled && rows2) launch(k_cg_update_tiled<P_F16, true, true>, g, s, ev, g, U, t, r, p, x, diag, st, partials);
+      else if (g.tiled) launch(k_cg_update_tiled<P_F16, false, true>, g, s, ev, g, U, t, r, p, x, diag, st, partials);
+      else launch(k_cg_update<P_F16, P_F32, false, true>, g, s, ev, g, U, t, r, p, x, diag, st, partials);
       break;
   }
   launch_finalize(g, partials, st, F_BETA, G_ITER, s);
 }
 
+// r update without the x and p terms (the mixed solver's deferred x update).
+template <int P>
+static void r_update_p(const Geom& g, const void* U, SpinorBuf t, SpinorBuf r, double diag, SolverState* st,
+                       double* partials, hipStream_t s, const EventPair* ev, int rows2) {
+  const SpinorBuf none{nullptr, nullptr, P};
+  if constexpr (P == P_BF16 || P == P_F16) {
+    if (g.tiled) {
+      if (rows2) launch(k_cg_update_tiled<P, true, false>, g, s, ev, g, U, t, r, none, none, diag, st, partials);
+      else launch(k_cg_update_tiled<P, false, false>, g, s, ev, g, U, t, r, none, none, diag, st, partials);
+      return;
+    }
+    launch(k_cg_update<P, P_F32, false, false>, g, s, ev, g, U, t, r, none, none, diag, st, partials);
+  } else {
+    if (g.tiled) launch(k_cg_update<P, P, true, false>, g, s, ev, g, U, t, r, none, none, diag, st, partials);
+    else launch(k_cg_update<P, P, false, false>, g, s, ev, g, U, t, r, none, none, diag, st, partials);
+  }
+}
+
+void launch_r_update(const Geom& g, int prec, const void* U, SpinorBuf t, SpinorBuf r, double mass, SolverState* st,
+                     double* partials, hipStream_t s, const EventPair* ev, int rows2) {
+  const double diag = mass + 4.0;
+  switch (prec) {
+    case P_F64: r_update_p<P_F64>(g, U, t, r, diag, st, partials, s, ev, 0); break;
+    case P_F32: r_update_p<P_F32>(g, U, t, r, diag, st, partials, s, ev, 0); break;
+    case P_BF16: r_update_p<P_BF16>(g, U, t, r, diag, st, partials, s, ev, rows2); break;
+    default: r_update_p<P_F16>(g, U, t, r, diag, st, partials, s, ev, rows2); break;
+  }
+  launch_finalize(g, partials, st, F_BETA, G_ITER, s);
+}
+
+void launch_p_update_ring(const Geom& g, SpinorBuf r, const RingBuf& ring, SolverState* st, hipStream_t s,
+                          const EventPair* ev) {
+  const SolverState* cst = st;
+  switch (ring.prec) {
+    case P_F64: launch(k_p_update_ring<P_F64>, g, s, ev, g, r, ring, cst); break;
+    case P_F32: launch(k_p_update_ring<P_F32>, g, s, ev, g, r, ring, cst); break;
+    case P_BF16: launch(k_p_update_ring<P_BF16>, g, s, ev, g, r, ring, cst); break;
+    default: launch(k_p_update_ring<P_F16>, g, s, ev, g, r, ring, cst); break;
+  }
+}
+
+void launch_accumulate_ring(const Geom& g, SpinorBuf x64, const RingBuf& ring, int gate, SolverState* st,
+                            hipStream_t s) {
+  const SolverState* cst = st;
+  switch (ring.prec) {
+    case P_F64: launch(k_accumulate_ring<P_F64>, g, s, nullptr, g, x64, ring, gate, cst); break;
+    case P_F32: launch(k_accumulate_ring<P_F32>, g, s, nullptr, g, x64, ring, gate, cst); break;
+    case P_BF16: launch(k_accumulate_ring<P_BF16>, g, s, nullptr, g, x64, ring, gate, cst); break;
+    default: launch(k_accumulate_ring<P_F16>, g, s, nullptr, g, x64, ring, gate, cst); break;
+  }
+}
+
+void launch_ring_reset(SolverState* st, hipStream_t s) { k_ring_reset<<<1, 64, 0, s>>>(st); }
+
+void launch_set_ring(SolverState* st, double* alpha_hist, int flush_at, int ring_len, hipStream_t s) {
+  k_set_ring<<<1, 64, 0, s>>>(st, alpha_hist, flush_at, ring_len);
+}
+
 void launch_residual(const Geom& g, const void* U64, SpinorBuf t64, SpinorBuf b64, SpinorBuf out, double mass,
                      int gate, int fin, SolverState* st, double* partials, hipStream_t s) {
   const double diag = mass + 4.0;
-  switch (out.prec) {
-    case P_F64: k_residual<P_F64><<<grid_of(g), kBlock, 0, s>>>(g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
-    case P_F32: k_residual<P_F32><<<grid_of(g), kBlock, 0, s>>>(g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
-    case P_BF16: k_residual<P_BF16><<<grid_of(g), kBlock, 0, s>>>(g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
-    default: k_residual<P_F16><<<grid_of(g), kBlock, 0, s>>>(g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
+  if (g.tiled) {
+    switch (out.prec) {
+      case P_F64: launch(k_residual<P_F64, true>, g, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
+      case P_F32: launch(k_residual<P_F32, true>, g, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
+      case P_BF16: launch(k_residual<P_BF16, true>, g, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
+      default: launch(k_residual<P_F16, true>, g, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
+    }
+  } else {
+    switch (out.prec) {
+      case P_F64: launch(k_residual<P_F64, false>, g, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
+      case P_F32: launch(k_residual<P_F32, false>, g, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
+      case P_BF16: launch(k_residual<P_BF16, false>, g, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
+      default: launch(k_residual<P_F16, false>, g, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
+    }
   }
   launch_finalize(g, partials, st, fin, gate, s);
 }

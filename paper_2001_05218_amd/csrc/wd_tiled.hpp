@@ -92,6 +92,62 @@ __device__ __forceinline__ void tile_stage(const Geom& g, int T, const void* Uv,
   }
 }
 
+// ---- FP64 / FP32 stencils on the tiled order. A workgroup owns one 4^4
+// tile; its 256 spinors are staged in LDS (48 KB in FP64) and the hops to
+// sites inside the tile read them there. A hop across a tile face reads the
+// neighbour from memory: each face site has a single consumer in this tile,
+// so staging it would not save a load.
+template <int P> struct TileWord;
+template <> struct TileWord<P_F64> { using T = double2; static constexpr int n = 12; };
+template <> struct TileWord<P_F32> { using T = float4; static constexpr int n = 6; };
+
+template <int P>
+struct TileSrc {
+  using Word = typename TileWord<P>::T;
+  using Real = typename PackedSpinor<P>::Real;
+  static constexpr int NW = TileWord<P>::n;
+  static constexpr bool kFence = true;
+  const Word* lds;       // [NW][256]
+  PackedSpinor<P> mem;
+  int T;
+  // One code path for both cases: a generic pointer into LDS (stride 256
+  // words) or into memory (stride 64 words within the site's block).
+  __device__ __forceinline__ void load(int s, Real v[24]) const {
+    const bool in_tile = (s >> 8) == T;
+    const Word* base = in_tile ? lds + (s & (kTileSites - 1)) : mem.data + word_index(s, NW, 0);
+    const int stride = in_tile ? kTileSites : kSiteBlock;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const Word d = base[w * stride];
+      if constexpr (P == P_F64) {
+        v[2 * w] = d.x;
+        v[2 * w + 1] = d.y;
+      } else {
+        v[4 * w] = d.x; v[4 * w + 1] = d.y; v[4 * w + 2] = d.z; v[4 * w + 3] = d.w;
+      }
+    }
+  }
+};
+
+// Copy tile T of `in` to LDS (one site per thread) and return the source; ends
+// with a barrier, so every thread of the workgroup must call it.
+template <int P>
+__device__ __forceinline__ TileSrc<P> stage_own_tile(const SpinorBuf& in, int T, typename TileWord<P>::T* lds) {
+  using Word = typename TileWord<P>::T;
+  constexpr int NW = TileWord<P>::n;
+  const Word* src = static_cast<const Word*>(in.data);
+  const int s = T * kTileSites + threadIdx.x;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) lds[w * kTileSites + threadIdx.x] = src[word_index(s, NW, w)];
+  __syncthreads();
+  TileSrc<P> t;
+  t.lds = lds;
+  t.mem.data = static_cast<Word*>(in.data);
+  t.mem.scale = in.scale;
+  t.T = T;
+  return t;
+}
+
 template <int P>
 __device__ __forceinline__ void tile_spinor(const TileLds<P>& lds, int slot, float v[24]) {
   uint4 d[3];

@@ -90,7 +90,7 @@ def wilson_force(a: torch.Tensor, b: torch.Tensor, coeff: float = 1.0, out: torc
 
 
 def make_params(tol=1e-10, max_iter=10000, inner="f64", reliable_interval=50, rhs="source", io_dtype=WD_C128,
-                zero_guess=True, history_len=0, profile=False, scheme="reliable", inner_tol=0.0):
+                zero_guess=True, history_len=0, profile=False, scheme="reliable", inner_tol=0.0, ring_len=0):
     p = _lib.WdCgParams()
     p.tol = float(tol)
     p.max_iter = int(max_iter)
@@ -107,6 +107,7 @@ def make_params(tol=1e-10, max_iter=10000, inner="f64", reliable_interval=50, rh
     p.profile = 1 if profile else 0
     p.scheme = {"reliable": 0, "refinement": 1}[scheme] if isinstance(scheme, str) else int(scheme)
     p.inner_tol = float(inner_tol)
+    p.ring_len = int(ring_len)
     return p, hist
 
 
@@ -121,20 +122,22 @@ def workspace_bytes(dims, params, nrhs=1) -> int:
 def cg_solve(U: torch.Tensor, b: torch.Tensor, mass: float, tol: float = 1e-10, max_iter: int = 10000,
              inner: str = "f64", reliable_interval: int = 50, rhs: str = "source", x0: torch.Tensor | None = None,
              history: int = 0, workspace: torch.Tensor | None = None, raise_on_nonconvergence: bool = True,
-             profile: bool = False, scheme: str = "reliable", inner_tol: float = 0.0):
+             profile: bool = False, scheme: str = "reliable", inner_tol: float = 0.0, ring_len: int = 0):
     """Solve D^+ D x = D^+ b (rhs="source") or D^+ D x = b (rhs="normal").
 
     Returns (x, info); info holds the wd_cg_result fields (and "history" if
     asked). complex64 b gives complex64 x (inner arithmetic unchanged).
     profile=True fills info["kernel_seconds"] with the inner loop's average
     kernel times. scheme="refinement" selects iterative refinement (defect
-    correction) instead of reliable updates for a mixed solve."""
+    correction) instead of reliable updates for a mixed solve. ring_len sets
+    how many search directions a mixed solve keeps before folding them into x
+    (0: the library default)."""
     dims = dims_of_spinor(b)
     _need(b, "b", (torch.complex128, torch.complex64), spinor_shape(dims))
     _need(U, "U", (torch.complex128,), gauge_shape(dims))
     io = WD_C64 if b.dtype == torch.complex64 else WD_C128
     params, hist = make_params(tol, max_iter, inner, reliable_interval, rhs, io, x0 is None, history, profile,
-                               scheme, inner_tol)
+                               scheme, inner_tol, ring_len)
     if x0 is None:
         x = torch.empty_like(b)
     else:

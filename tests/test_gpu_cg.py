@@ -195,3 +195,42 @@ def test_iterative_refinement(inner):
     _, ru = wd.cg_solve(Ut, bt, 0.02, tol=TOL, inner=inner)
     # restarts lose the Krylov history: never fewer iterations than reliable updates
     assert info["iterations"] >= ru["iterations"]
+
+
+@pytest.mark.parametrize("inner,ring_len,interval", [("f16", 8, 100), ("f16", 256, 50), ("f32", 8, 50),
+                                                     ("bf16", 12, 1000)])
+def test_mixed_ring_lengths(inner, ring_len, interval):
+    """A mixed solve keeps each iteration's search direction in a ring and
+    folds sum_j alpha_j p_j into the FP64 x at reliable updates, or as soon as
+    ring_len - 4 directions are pending (ring 8 with updates every 100
+    iterations folds about every 5 iterations). The fold only changes the
+    rounding of x: the solve converges like the default ring."""
+    dims = (8, 8, 8, 16)
+    log(f"cg ring {inner} ring_len={ring_len} interval={interval}")
+    U, b = _fields(dims, "near_identity", 73)
+    Ut, bt = to_dev(U), to_dev(b)
+    x, info = wd.cg_solve(Ut, bt, 0.02, tol=TOL, inner=inner, reliable_interval=interval, ring_len=ring_len)
+    x0, info0 = wd.cg_solve(Ut, bt, 0.02, tol=TOL, inner=inner, reliable_interval=interval)
+    xn = to_np(x)
+    res = _true_res(U, xn, b, 0.02)
+    log(f"  iterations={info['iterations']} (default ring {info0['iterations']}) "
+        f"updates={info['reliable_updates']} true_res={res:.3e}")
+    assert res <= TOL * (1 + 1e-3)
+    assert abs(res - info["true_rel_res"]) <= 1e-13
+    assert abs(info["iterations"] - info0["iterations"]) <= 0.1 * info0["iterations"] + 2
+    assert rel(xn, to_np(x0)) <= ((0.02 + 8) / 0.02) ** 2 * 2 * TOL
+
+
+def test_mixed_not_converged_folds_ring():
+    """At max_iter the pending directions are folded into x before the final
+    FP64 residual: the reported residual is that of the returned x."""
+    dims = (8, 8, 8, 8)
+    U, b = _fields(dims, "near_identity", 75)
+    Ut, bt = to_dev(U), to_dev(b)
+    x, info = wd.cg_solve(Ut, bt, 0.02, tol=TOL, inner="f16", max_iter=37, ring_len=64,
+                          raise_on_nonconvergence=False)
+    assert info["status"] == _lib.WD_NOT_CONVERGED
+    assert info["iterations"] == 37
+    res = _true_res(U, to_np(x), b, 0.02)
+    assert abs(res - info["true_rel_res"]) <= 1e-12 * max(1.0, res)
+    assert res < 0.5

@@ -58,6 +58,7 @@ def _params(**kw):
     p.history_len = kw.get("history_len", 0)
     p.scheme = kw.get("scheme", 0)
     p.inner_tol = kw.get("inner_tol", 0.0)
+    p.ring_len = kw.get("ring_len", 0)
     return p
 
 
@@ -90,6 +91,7 @@ def test_force_rejects_bad_args(lib):
     (dict(inner_prec=7), "inner_prec"), (dict(rhs_mode=3), "rhs_mode"), (dict(io_dtype=5), "io_dtype"),
     (dict(reliable_interval=-1), "reliable_interval"), (dict(history_len=4), "history"),
     (dict(scheme=2), "scheme"), (dict(inner_tol=1.5), "inner_tol"), (dict(inner_tol=-0.1), "inner_tol"),
+    (dict(ring_len=7), "ring_len"), (dict(ring_len=257), "ring_len"), (dict(ring_len=-1), "ring_len"),
 ])
 def test_cg_rejects_bad_params(lib, kw, msg):
     p = _params(**kw)
@@ -151,3 +153,17 @@ def test_product_path_never_touches_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"\b(import|from)\s+oracle\b", text), f
                 assert "oracle/" not in text, f
+
+
+def test_workspace_grows_with_ring(lib):
+    """A mixed solve keeps ring_len low-precision search directions in the
+    workspace (FP16: 48 B + a 4 B scale per site each); FP64 CG keeps none."""
+    dims = (8, 8, 8, 8)
+    V = 8 ** 4
+    a = lib.wd_workspace_bytes(_lat(dims), ctypes.byref(_params(inner_prec=3, ring_len=100)), 1)
+    b = lib.wd_workspace_bytes(_lat(dims), ctypes.byref(_params(inner_prec=3, ring_len=200)), 1)
+    assert b - a >= 100 * 52 * V
+    assert b - a < 100 * 52 * V + 4096
+    c = lib.wd_workspace_bytes(_lat(dims), ctypes.byref(_params(inner_prec=0, ring_len=8)), 1)
+    d = lib.wd_workspace_bytes(_lat(dims), ctypes.byref(_params(inner_prec=0, ring_len=40)), 1)
+    assert c == d
