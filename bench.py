@@ -77,11 +77,12 @@ PROFILES = os.path.join(ROOT, "profiles")
 
 
 def kernel_source_sha() -> str:
-    """SHA-256 over the HIP sources: a stored counter figure is only valid for
-    the kernels it was measured on."""
+    """SHA-256 over the device-code sources (.hip and headers; the host-only
+    .cpp is left out): a stored counter figure is only valid for the kernels
+    it was measured on."""
     h = hashlib.sha256()
     for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".hpp", ".cpp")):
+        if name.endswith((".hip", ".hpp")):
             with open(os.path.join(CSRC, name), "rb") as f:
                 h.update(name.encode())
                 h.update(f.read())

@@ -97,10 +97,12 @@ typedef struct {
                                 events on `stream` over the first 64 iterations (see wd_cg_result) */
   int32_t scheme;            /* WD_RELIABLE_UPDATE or WD_ITERATIVE_REFINEMENT (cg_solve, mixed) */
   int32_t ring_len;          /* mixed (cg_solve): search directions kept in the workspace before
-                                they are folded into x (x += sum alpha_j p_j, in FP64); 0 -> 32,
-                                else 8..256. The fold runs at each FP64 recomputation and
-                                whenever ring_len - 4 directions are pending. Workspace grows by
-                                ring_len low-precision spinors. */
+                                they are folded into x (x += sum alpha_j p_j, in FP64); 8..256, or
+                                0 -> reliable_interval + 5 (so that folds coincide with the FP64
+                                recomputations) limited to what fits in 8 GiB, at least 8. The
+                                fold runs at each FP64 recomputation and whenever ring_len - 4
+                                directions are pending. Workspace grows by ring_len
+                                low-precision spinors. */
   double inner_tol;          /* residual reduction between FP64 recomputations; 0 -> the default
                                 (reliable updates: 0.1 BF16, 1e-2 FP16, 1e-4 FP32; refinement: 0.1) */
 } wd_cg_params;

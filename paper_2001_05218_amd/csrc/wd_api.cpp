@@ -101,10 +101,23 @@ struct CgWorkspace {
   size_t bytes;
 };
 
-constexpr int kDefaultRing = 32;
 constexpr int kSlotEvery = 5;   // mixed: a reliable-update slot after every 5th enqueued iteration
+constexpr size_t kRingBudget = size_t(8) << 30;   // default ring: at most 8 GiB
 
-int ring_length(const wd_cg_params* p) { return p->ring_len > 0 ? p->ring_len : kDefaultRing; }
+int reliable_interval_of(const wd_cg_params* p) {
+  if (p->scheme == WD_ITERATIVE_REFINEMENT) return 1 << 30;   // no periodic recomputation
+  return p->reliable_interval > 0 ? p->reliable_interval : 50;
+}
+
+// Ring slots: the caller's ring_len, else enough that the ring is folded only
+// at reliable updates (interval + kSlotEvery), within kRingBudget bytes.
+int ring_length(const wd_cg_params* p, const Geom& g) {
+  if (p->ring_len > 0) return p->ring_len;
+  const size_t per = align_up(spinor_bytes(p->inner_prec, g.Vpad)) + align_up(spinor_scale_bytes(p->inner_prec, g.Vpad));
+  const long long by_mem = (long long)(kRingBudget / per);
+  const long long want = std::min<long long>((long long)reliable_interval_of(p) + kSlotEvery, by_mem);
+  return (int)std::max<long long>(8, std::min<long long>(256, want));
+}
 
 CgWorkspace layout_cg(void* base, const Geom& g, int inner, int hist_len, int ring_len) {
   Carver c(base);
@@ -258,7 +271,7 @@ int validate_params(const wd_cg_params* p) {
 size_t required_bytes(const Geom& g, const wd_cg_params* p, int nrhs) {
   const size_t batched = batched_workspace_bytes(g, nrhs, p->history_len);
   if (nrhs == 1)
-    return std::max(layout_cg(nullptr, g, p->inner_prec, p->history_len, ring_length(p)).bytes, batched);
+    return std::max(layout_cg(nullptr, g, p->inner_prec, p->history_len, ring_length(p, g)).bytes, batched);
   return batched;
 }
 
@@ -498,7 +511,7 @@ int cg_setup(const Geom& g, double mass, const void* U, const void* b, void* x, 
 
 int cg_plain(const Geom& g, double mass, const void* U, const void* b, void* x, const wd_cg_params* p,
              wd_cg_result* res, void* ws, hipStream_t s, std::chrono::steady_clock::time_point t0) {
-  const CgWorkspace w = layout_cg(ws, g, WD_F64, p->history_len, ring_length(p));
+  const CgWorkspace w = layout_cg(ws, g, WD_F64, p->history_len, ring_length(p, g));
   int rc = cg_setup(g, mass, U, b, x, p, w, 0, 0.0, w.r64, s);
   if (rc) return rc;
   launch_convert(g, w.r64, w.p64, G_ALWAYS, w.st, s);
@@ -581,8 +594,8 @@ int cg_mixed(const Geom& g, double mass, const void* U, const void* b, void* x, 
   const int P = p->inner_prec;
   const bool refine = p->scheme == WD_ITERATIVE_REFINEMENT;
   // refinement: no periodic recomputation, only after each inner solve
-  const int interval = refine ? (1 << 30) : (p->reliable_interval > 0 ? p->reliable_interval : 50);
-  const CgWorkspace w = layout_cg(ws, g, P, p->history_len, ring_length(p));
+  const int interval = reliable_interval_of(p);
+  const CgWorkspace w = layout_cg(ws, g, P, p->history_len, ring_length(p, g));
   // Besides every `interval` iterations, recompute the residual whenever the
   // iterated residual has fallen by `delta` since the last update, so that
   // the low-precision drift (~ unit roundoff x the residual at the last
