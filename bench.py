@@ -2,7 +2,7 @@
 """Benchmark: CG time-to-solution (mixed precision vs FP64) and Dslash HBM
 bandwidth for the Wilson-Dirac normal equations on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--inner auto|bf16|f16|f32]
+    python bench.py [--steps K] [--warmup W] [--inner auto|bf16|f16|i8|f32]
 
 Workload: 32^3 x 64 periodic lattice, links exp(i 0.3 H) (H a Gaussian
 combination of Gell-Mann matrices), m = 0.02, one Gaussian complex128
@@ -41,7 +41,7 @@ TOL = 1e-10
 # algorithmic bytes per site of one Wilson application (each link and spinor
 # moved once; 4 links x 9 complex + spinor in + spinor out)
 BYTES_PER_SITE = {"f64": 4 * 9 * 16 + 2 * 192, "f32": 4 * 9 * 8 + 2 * 96, "bf16": 4 * 9 * 4 + 2 * 48,
-                  "f16": 4 * 9 * 4 + 2 * 48 + 2 * 4}
+                  "f16": 4 * 9 * 4 + 2 * 48 + 2 * 4, "i8": 4 * 9 * 4 + 2 * 24 + 2 * 4}
 FLOPS_PER_SITE = 1368
 # algorithmic bytes per site of the inner loop's kernels, by storage:
 #   D p       : 4 links + p in + t out
@@ -51,8 +51,8 @@ FLOPS_PER_SITE = 1368
 #               at reliable updates: per iteration one more read of p plus
 #               1/len of an FP64 x read and write, outside these kernels)
 #   p update  : r in + p in + p out
-SPINOR_B = {"f64": 192, "f32": 96, "bf16": 48, "f16": 52}
-LINKS_B = {"f64": 576, "f32": 288, "bf16": 144, "f16": 144}
+SPINOR_B = {"f64": 192, "f32": 96, "bf16": 48, "f16": 52, "i8": 28}
+LINKS_B = {"f64": 576, "f32": 288, "bf16": 144, "f16": 144, "i8": 144}
 
 
 def loop_kernel_bytes(prec, two_row_links=False):
@@ -67,10 +67,10 @@ def loop_kernel_bytes(prec, two_row_links=False):
 
 KERNEL_NAMES = {  # kernel that runs each loop step for a storage precision (tiled lattice)
     "D": {"f64": "k_wilson_packed_f64", "f32": "k_wilson_packed_f32", "bf16": "k_wilson_tiled_bf16",
-          "f16": "k_wilson_tiled_f16"},
+          "f16": "k_wilson_tiled_f16", "i8": "k_wilson_tiled_i8"},
     "update": {"f64": "k_cg_update_f64", "f32": "k_cg_update_f32", "bf16": "k_cg_update_tiled_bf16",
-               "f16": "k_cg_update_tiled_f16"},
-    "p_update": {p: f"k_p_update_{p}" for p in ("f64", "f32", "bf16", "f16")},
+               "f16": "k_cg_update_tiled_f16", "i8": "k_cg_update_tiled_i8"},
+    "p_update": {p: f"k_p_update_{p}" for p in ("f64", "f32", "bf16", "f16", "i8")},
 }
 CSRC = os.path.join(ROOT, "paper_2001_05218_amd", "csrc")
 PROFILES = os.path.join(ROOT, "profiles")
@@ -115,7 +115,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--inner", default="auto", choices=["auto", "bf16", "f16", "f32"])
+    ap.add_argument("--inner", default="auto", choices=["auto", "bf16", "f16", "i8", "f32"])
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--dslash-reps", type=int, default=200)
     ap.add_argument("--dims", default=",".join(str(d) for d in DIMS))
@@ -207,13 +207,13 @@ def main():
         return x, info, time.perf_counter() - t
 
     ws = {}
-    for inner in ("f64", "f32", "bf16", "f16"):
+    for inner in ("f64", "f32", "bf16", "f16", "i8"):
         p, _ = wd.ops.make_params(TOL, 20000, inner, 50, "source")
         ws[inner] = torch.empty(wd.workspace_bytes(dims, p), dtype=torch.uint8, device=dev)
         del p
 
     # candidates for the headline inner precision
-    cands = ["bf16", "f16", "f32"] if args.inner == "auto" else [args.inner]
+    cands = ["bf16", "f16", "i8", "f32"] if args.inner == "auto" else [args.inner]
     variants = {}
     for inner in cands:
         for _ in range(max(1, args.warmup)):

@@ -51,12 +51,16 @@ typedef struct {
   int32_t L[4]; /* Lx, Ly, Lz, Lt; each >= 2; Lx*Ly*Lz*Lt <= 2^28 */
 } wd_lattice;
 
-/* storage / arithmetic precision of the solver's inner iterations */
-enum { WD_F64 = 0, WD_F32 = 1, WD_BF16 = 2, WD_F16 = 3 };
+/* storage / arithmetic precision of the solver's inner iterations.
+ * WD_F16 spinors carry one FP32 magnitude per site (values stored divided by it).
+ * WD_I8 is fixed point: spinors as 24 bytes per site, b = 128 + round(127 v / m)
+ * with m the site's largest |component| (kept as FP32 per site); links as int16
+ * q = round(16384 u), so entries must lie within +-2 (larger ones saturate). */
+enum { WD_F64 = 0, WD_F32 = 1, WD_BF16 = 2, WD_F16 = 3, WD_I8 = 4 };
 /* OR-ed into the precision of a packed GAUGE field (wd_gauge_bytes, wd_pack_gauge,
  * wilson_apply_packed): store rows 0 and 1 of each link only and rebuild row 2
  * as conj(row0 x row1). Valid for SU(3) links (the caller guarantees it),
- * WD_BF16 / WD_F16, and lattices whose extents are all multiples of 4. */
+ * WD_BF16 / WD_F16 / WD_I8, and lattices whose extents are all multiples of 4. */
 enum { WD_TWO_ROW_LINKS = 0x100 };
 /* which system cg_solve solves */
 enum { WD_RHS_SOURCE = 0, /* D^+ D x = D^+ b  (x = D^-1 b) */
@@ -84,7 +88,7 @@ enum {
 typedef struct {
   double tol;                /* stop when ||b' - D^+ D x|| / ||b'|| <= tol (b' = D^+ b or b) */
   int32_t max_iter;          /* CG iterations (inner iterations for mixed precision) */
-  int32_t inner_prec;        /* WD_F64: plain FP64 CG. WD_F32 / WD_BF16 / WD_F16: FP32
+  int32_t inner_prec;        /* WD_F64: plain FP64 CG. WD_F32 / WD_BF16 / WD_F16 / WD_I8: FP32
                                 arithmetic on that storage, FP64 reliable updates */
   int32_t reliable_interval; /* mixed only: FP64 residual recomputation every this many
                                 iterations (0 -> 50) */
@@ -104,7 +108,8 @@ typedef struct {
                                 directions are pending. Workspace grows by ring_len
                                 low-precision spinors. */
   double inner_tol;          /* residual reduction between FP64 recomputations; 0 -> the default
-                                (reliable updates: 0.1 BF16, 1e-2 FP16, 1e-4 FP32; refinement: 0.1) */
+                                (reliable updates: 0.1 BF16 and I8, 1e-2 FP16, 1e-4 FP32;
+                                refinement: 0.1) */
 } wd_cg_params;
 
 typedef struct {
@@ -112,7 +117,7 @@ typedef struct {
   int32_t reliable_updates;  /* FP64 residual recomputations (mixed) */
   int32_t status;            /* same value as the call's return code */
   int32_t two_row_links;     /* 1 if the inner iterations used two-row (12-real) links: cg_solve does
-                                so for WD_BF16 / WD_F16 on tileable lattices whose links are SU(3)
+                                so for WD_BF16 / WD_F16 / WD_I8 on tileable lattices whose links are SU(3)
                                 to 1e-9 (checked on the device); 0 otherwise */
   double true_rel_res;       /* ||b' - D^+ D x|| / ||b'|| recomputed in FP64 at the end */
   double iter_rel_res;       /* the recurrence's own residual at the end */
@@ -206,7 +211,7 @@ int wd_unpack_spinor(const wd_lattice* lat, const void* in, int32_t prec, void* 
                      void* stream);
 
 /* out = D in (dagger = 0) or D^+ in on packed fields of precision prec (FP32
- * arithmetic for WD_F32/WD_BF16/WD_F16, FP64 for WD_F64). The kernel of the
+ * arithmetic for WD_F32/WD_BF16/WD_F16/WD_I8, FP64 for WD_F64). The kernel of the
  * solver's inner iterations. Asynchronous. */
 int wilson_apply_packed(const wd_lattice* lat, double mass, int32_t prec, const void* U_packed,
                         const void* in_packed, void* out_packed, int32_t dagger, void* stream);

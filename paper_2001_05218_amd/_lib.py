@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwilson_mi355x.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "wilson.h")
 
-WD_F64, WD_F32, WD_BF16, WD_F16 = 0, 1, 2, 3
+WD_F64, WD_F32, WD_BF16, WD_F16, WD_I8 = 0, 1, 2, 3, 4
 WD_RHS_SOURCE, WD_RHS_NORMAL = 0, 1
 WD_C128, WD_C64 = 0, 1
 WD_TWO_ROW_LINKS = 0x100
@@ -23,8 +23,9 @@ WD_RELIABLE_UPDATE, WD_ITERATIVE_REFINEMENT = 0, 1
 WD_OK, WD_NOT_CONVERGED = 0, 1
 WD_ERR_INVALID, WD_ERR_HIP, WD_ERR_BREAKDOWN, WD_ERR_NAN, WD_ERR_WORKSPACE = -1, -2, -3, -4, -5
 
-PREC_NAMES = {"f64": WD_F64, "f32": WD_F32, "bf16": WD_BF16, "f16": WD_F16,
-              "bf16_rows2": WD_BF16 | WD_TWO_ROW_LINKS, "f16_rows2": WD_F16 | WD_TWO_ROW_LINKS}
+PREC_NAMES = {"f64": WD_F64, "f32": WD_F32, "bf16": WD_BF16, "f16": WD_F16, "i8": WD_I8,
+              "bf16_rows2": WD_BF16 | WD_TWO_ROW_LINKS, "f16_rows2": WD_F16 | WD_TWO_ROW_LINKS,
+              "i8_rows2": WD_I8 | WD_TWO_ROW_LINKS}
 
 
 class WdLattice(ctypes.Structure):

@@ -60,7 +60,11 @@ int check_lattice(const wd_lattice* lat) {
 // extent is a multiple of 4.
 Geom packed_geom(const wd_lattice* lat) { return make_geom(lat->L, true); }
 
-bool valid_prec(int p) { return p == WD_F64 || p == WD_F32 || p == WD_BF16 || p == WD_F16; }
+bool valid_prec(int p) { return p == WD_F64 || p == WD_F32 || p == WD_BF16 || p == WD_F16 || p == WD_I8; }
+
+// Low-precision storage whose links may be kept as two rows (and whose tiled
+// kernels stage 16-bit or 8-bit words).
+bool narrow_prec(int p) { return p == WD_BF16 || p == WD_F16 || p == WD_I8; }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
@@ -82,7 +86,7 @@ SpinorBuf take_spinor(Carver& c, int prec, const Geom& g) {
   SpinorBuf b;
   b.prec = prec;
   b.data = c.take(spinor_bytes(prec, g.Vpad));
-  b.scale = prec == P_F16 ? static_cast<float*>(c.take(spinor_scale_bytes(prec, g.Vpad))) : nullptr;
+  b.scale = spinor_scale_bytes(prec, g.Vpad) ? static_cast<float*>(c.take(spinor_scale_bytes(prec, g.Vpad))) : nullptr;
   return b;
 }
 
@@ -141,7 +145,7 @@ CgWorkspace layout_cg(void* base, const Geom& g, int inner, int hist_len, int ri
     w.ring.len = ring_len;
     w.ring.stride = (long long)align_up(spinor_bytes(inner, g.Vpad));
     w.ring.data = static_cast<char*>(c.take((size_t)w.ring.stride * ring_len));
-    if (inner == WD_F16) {
+    if (spinor_scale_bytes(inner, g.Vpad)) {
       w.ring.scale_stride = (long long)align_up(spinor_scale_bytes(inner, g.Vpad));
       w.ring.scale = static_cast<char*>(c.take((size_t)w.ring.scale_stride * ring_len));
     }
@@ -319,8 +323,8 @@ static int gauge_format(const wd_lattice* lat, int32_t prec, int* rows2) {
   *rows2 = (prec & WD_TWO_ROW_LINKS) ? 1 : 0;
   const int p = prec & ~WD_TWO_ROW_LINKS;
   if (!valid_prec(p)) return fail(WD_ERR_INVALID, "prec = %d unknown", prec);
-  if (*rows2 && !(p == WD_BF16 || p == WD_F16))
-    return fail(WD_ERR_INVALID, "two-row links exist for WD_BF16 and WD_F16 only");
+  if (*rows2 && !narrow_prec(p))
+    return fail(WD_ERR_INVALID, "two-row links exist for WD_BF16, WD_F16 and WD_I8 only");
   if (*rows2 && !packed_geom(lat).tiled)
     return fail(WD_ERR_INVALID, "two-row links need every lattice extent to be a multiple of 4");
   return WD_OK;
@@ -346,8 +350,9 @@ static SpinorBuf packed_view(const Geom& g, int prec, const void* p) {
   SpinorBuf b;
   b.prec = prec;
   b.data = const_cast<void*>(p);
-  b.scale = prec == P_F16 ? reinterpret_cast<float*>(static_cast<char*>(b.data) + spinor_bytes(prec, g.Vpad))
-                          : nullptr;
+  b.scale = spinor_scale_bytes(prec, g.Vpad)
+                ? reinterpret_cast<float*>(static_cast<char*>(b.data) + spinor_bytes(prec, g.Vpad))
+                : nullptr;
   return b;
 }
 
@@ -600,7 +605,7 @@ int cg_mixed(const Geom& g, double mass, const void* U, const void* b, void* x, 
   // iterated residual has fallen by `delta` since the last update, so that
   // the low-precision drift (~ unit roundoff x the residual at the last
   // update) stays well below the residual being iterated.
-  double delta = (P == WD_BF16) ? 0.1 : (P == WD_F16) ? 1e-2 : 1e-4;
+  double delta = (P == WD_BF16 || P == WD_I8) ? 0.1 : (P == WD_F16) ? 1e-2 : 1e-4;
   if (refine) delta = 0.1;
   if (p->inner_tol > 0.0) delta = p->inner_tol;
   int rc = cg_setup(g, mass, U, b, x, p, w, interval, delta, w.rh, s);
@@ -611,7 +616,7 @@ int cg_mixed(const Geom& g, double mass, const void* U, const void* b, void* x, 
   // 16-bit inner links: two rows per link (row 2 rebuilt from unitarity) when
   // every link is SU(3) to 1e-9; the full 9 entries otherwise.
   int rows2 = 0;
-  if ((P == WD_BF16 || P == WD_F16) && g.tiled) {
+  if (narrow_prec(P) && g.tiled) {
     launch_su3_check(g, U, w.st, w.partials, s);
     HIP_TRY(hipMemcpyAsync(m->buf[0], w.st, sizeof(SolverState), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));

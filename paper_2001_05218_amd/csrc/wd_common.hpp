@@ -24,7 +24,13 @@
 
 namespace wd {
 
-enum Prec : int { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_F16 = 3 };
+enum Prec : int { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_F16 = 3, P_I8 = 4 };
+
+// Storage formats that carry one FP32 magnitude per site next to the spinor.
+template <int P> constexpr bool kScaled = (P == P_F16 || P == P_I8);
+// 16-byte-or-smaller word of a packed low-precision spinor (3 words per site).
+template <int P> struct SpinorWord { using T = uint4; };   // BF16, FP16: 8 values per word
+template <> struct SpinorWord<P_I8> { using T = uint2; };  // int8: 8 values per word
 
 constexpr int kBlock = 256;      // threads per workgroup (4 wavefronts)
 constexpr int kSiteBlock = 64;   // sites per layout block (one wavefront)
@@ -215,11 +221,18 @@ __device__ __forceinline__ float h_bits2f(uint32_t b) {
   return (float)__builtin_bit_cast(_Float16, (uint16_t)(b & 0xffffu));
 }
 
-template <int P> struct PrecTraits;
-template <> struct PrecTraits<P_F64> { using Real = double; static constexpr int spinor_words = 12; static constexpr int link_word_bytes = 16; };
-template <> struct PrecTraits<P_F32> { using Real = float;  static constexpr int spinor_words = 6;  static constexpr int link_word_bytes = 8; };
-template <> struct PrecTraits<P_BF16> { using Real = float; static constexpr int spinor_words = 3;  static constexpr int link_word_bytes = 4; };
-template <> struct PrecTraits<P_F16> { using Real = float;  static constexpr int spinor_words = 3;  static constexpr int link_word_bytes = 4; };
+// Fixed-point links of the int8 storage: each real as an int16 q, value
+// q / kLinkFix (range +-2, resolution 6.1e-5); a pair (re low, im high) per word.
+constexpr float kLinkFix = 16384.0f;
+__device__ __forceinline__ int fix16(float v) {
+  return (int)rintf(fminf(fmaxf(v * kLinkFix, -32767.0f), 32767.0f));
+}
+__device__ __forceinline__ uint32_t pack_i16x2(float lo, float hi) {
+  return ((uint32_t)fix16(lo) & 0xffffu) | ((uint32_t)fix16(hi) << 16);
+}
+__device__ __forceinline__ float i16_bits2f(uint32_t b) {
+  return (float)(int)(int16_t)(uint16_t)(b & 0xffffu) * (1.0f / kLinkFix);
+}
 
 __device__ __forceinline__ size_t word_index(int s, int nwords, int w) {
   return ((size_t)(s >> 6) * nwords + w) * kSiteBlock + (s & 63);
@@ -366,6 +379,69 @@ template <> struct PackedSpinor<P_F16> {
   }
 };
 
+// int8 storage: value = (b - 128) * scale / 127 for the stored byte b
+// (offset binary, b in 1..255), scale = the site's largest |component|, so
+// unpacking a value is one byte-to-float convert and one FMA. A site with a
+// NaN or Inf component gets a NaN scale (it stays NaN when read back).
+template <> struct PackedSpinor<P_I8> {
+  using Real = float;
+  static constexpr bool kFence = false;
+  uint2* data;
+  float* scale;
+  static __device__ __forceinline__ void unpack(const uint2 d[3], float sc, Real v[24]) {
+    const float f = sc * (1.0f / 127.0f);
+    const float off = -128.0f * f;
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+      const uint32_t u[2] = {d[w].x, d[w].y};
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) v[8 * w + 4 * k + b] = fmaf((float)((u[k] >> (8 * b)) & 0xffu), f, off);
+    }
+  }
+  static __device__ __forceinline__ void pack(const Real v[24], uint2 d[3], float& sc) {
+    float m = 0.f, chk = 0.f;
+#pragma unroll
+    for (int i = 0; i < 24; ++i) {
+      m = fmaxf(m, fabsf(v[i]));
+      chk = fmaf(v[i], 0.f, chk);   // NaN if any component is NaN or Inf
+    }
+    const float inv = (m > 0.f) ? 127.0f / m : 0.f;
+    sc = (chk == 0.f) ? m : __builtin_nanf("");
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+      uint32_t u[2] = {0u, 0u};
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int q = (int)rintf(fminf(fmaxf(v[8 * w + 4 * k + b] * inv, -127.f), 127.f));
+          u[k] |= (uint32_t)(q + 128) << (8 * b);
+        }
+      d[w] = make_uint2(u[0], u[1]);
+    }
+  }
+  __device__ __forceinline__ float load_scale(int s) const { return scale[s]; }
+  __device__ __forceinline__ void load(int s, Real v[24]) const {
+    uint2 d[3];
+#pragma unroll
+    for (int w = 0; w < 3; ++w) d[w] = data[word_index(s, 3, w)];
+    unpack(d, scale[s], v);
+  }
+  __device__ __forceinline__ void store_raw(int s, const uint2 d[3], float sc) const {
+    scale[s] = sc;
+#pragma unroll
+    for (int w = 0; w < 3; ++w) data[word_index(s, 3, w)] = d[w];
+  }
+  __device__ __forceinline__ void store(int s, const Real v[24]) const {
+    uint2 d[3];
+    float sc;
+    pack(v, d, sc);
+    store_raw(s, d, sc);
+  }
+};
+
 // Canonical boundary layout: (Lt, Lz, Ly, Lx, 4, 3) complex128, AoS.
 struct CanonSpinor {
   using Real = double;
@@ -433,6 +509,9 @@ template <int P> __device__ __forceinline__ void unpack_link16(uint32_t d, float
   if constexpr (P == P_BF16) {
     re = bf_bits2f(d & 0xffffu);
     im = bf_bits2f(d >> 16);
+  } else if constexpr (P == P_I8) {
+    re = i16_bits2f(d);
+    im = i16_bits2f(d >> 16);
   } else {
     re = h_bits2f(d);
     im = h_bits2f(d >> 16);
@@ -467,6 +546,20 @@ template <> struct PackedGauge<P_F16> {
   }
 };
 
+template <> struct PackedGauge<P_I8> {   // int16 fixed-point links
+  using Real = float;
+  WD_GAUGE_FORWARDERS
+  const uint32_t* data;
+  __device__ __forceinline__ void load(int s, int mu, Real u[18]) const {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      uint32_t d = data[word_index(s, 36, mu * 9 + e)];
+      u[2 * e] = i16_bits2f(d);
+      u[2 * e + 1] = i16_bits2f(d >> 16);
+    }
+  }
+};
+
 // Canonical boundary layout: (4, Lt, Lz, Ly, Lx, 3, 3) complex128.
 struct CanonGauge {
   using Real = double;
@@ -489,10 +582,11 @@ inline size_t spinor_bytes(int P, int Vpad) {
   switch (P) {
     case P_F64: return (size_t)Vpad * 192;
     case P_F32: return (size_t)Vpad * 96;
+    case P_I8: return (size_t)Vpad * 24;
     default: return (size_t)Vpad * 48;
   }
 }
-inline size_t spinor_scale_bytes(int P, int Vpad) { return P == P_F16 ? (size_t)Vpad * 4 : 0; }
+inline size_t spinor_scale_bytes(int P, int Vpad) { return (P == P_F16 || P == P_I8) ? (size_t)Vpad * 4 : 0; }
 inline size_t gauge_bytes(int P, int Vpad) {
   switch (P) {
     case P_F64: return (size_t)Vpad * 4 * 9 * 16;

@@ -126,7 +126,8 @@ void launch_wilson_packed(const Geom& g, int prec, const void* U, SpinorBuf in, 
 void launch_pack_gauge_rows2(const Geom& g, const void* U_c128, int prec, void* out, hipStream_t s);
 // su3_dev = largest deviation of a canonical complex128 gauge field from SU(3).
 void launch_su3_check(const Geom& g, const void* U_c128, SolverState* st, double* partials, hipStream_t s);
-// q = D^+ t (never stored); r -= alpha q; x += alpha p; ||r||^2 -> F_BETA.
+// Plain CG (FP64 or FP32 storage): q = D^+ t (never stored); r -= alpha q;
+// x += alpha p; ||r||^2 -> F_BETA.
 void launch_cg_update(const Geom& g, int prec, const void* U, SpinorBuf t, SpinorBuf r, SpinorBuf p, SpinorBuf x,
                       double mass, SolverState* st, double* partials, hipStream_t s, const EventPair* ev = nullptr,
                       int rows2 = 0);

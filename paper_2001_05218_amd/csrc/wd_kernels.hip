@@ -204,6 +204,8 @@ __global__ __launch_bounds__(kBlock) void k_pack_gauge(Geom g, const double2* __
       else if constexpr (P == P_F32) reinterpret_cast<float2*>(out)[w] = make_float2((float)d.x, (float)d.y);
       else if constexpr (P == P_BF16)
         reinterpret_cast<uint32_t*>(out)[w] = pack_bf16x2((float)d.x, (float)d.y);
+      else if constexpr (P == P_I8)
+        reinterpret_cast<uint32_t*>(out)[w] = pack_i16x2((float)d.x, (float)d.y);
       else
         reinterpret_cast<uint32_t*>(out)[w] = pack_f16x2((float)d.x, (float)d.y);
     }
@@ -221,6 +223,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_gauge_rows2(Geom g, const doubl
     for (int e = 0; e < 6; ++e) {
       const double2 d = src[e];
       out[word_index(s, 24, mu * 6 + e)] = (P == P_BF16) ? pack_bf16x2((float)d.x, (float)d.y)
+                                           : (P == P_I8) ? pack_i16x2((float)d.x, (float)d.y)
                                                          : pack_f16x2((float)d.x, (float)d.y);
     }
   }
@@ -417,13 +420,12 @@ __global__ __launch_bounds__(kBlock) WD_TILED_OCCUPANCY void k_wilson_tiled(Geom
   }
 }
 
-// CG update with the LDS-staged D^+ (16-bit storage, tiled order). With XP
-// the kernel also does x += alpha p; without it (the fused loop) that update
-// is left to the next iteration's p update, which reads p anyway.
-template <int P, bool C12, bool XP>
+// r update of the mixed solver with the LDS-staged D^+ (16- or 8-bit
+// storage, tiled order): q = D^+ t (never stored), r -= alpha q, ||r||^2. The
+// solution update is deferred (the search directions wait in a ring).
+template <int P, bool C12>
 __global__ __launch_bounds__(kBlock) WD_TILED_OCCUPANCY void k_cg_update_tiled(Geom g, const void* U, SpinorBuf t, SpinorBuf r,
-                                                            SpinorBuf p, SpinorBuf x, double diag, SolverState* st,
-                                                            double* partials) {
+                                                            double diag, SolverState* st, double* partials) {
   if (!gate_open(st, G_ITER)) return;
   __shared__ TileLds<P> lds;
   const int T = xcd_tile(blockIdx.x, gridDim.x);
@@ -437,14 +439,6 @@ __global__ __launch_bounds__(kBlock) WD_TILED_OCCUPANCY void k_cg_update_tiled(G
   float rv[24];
   const auto rs = spinor_of<P>(r);
   rs.load(s, rv);
-  if constexpr (XP) {
-    float pv[24], xv[24];
-    spinor_of<P>(p).load(s, pv);
-    spinor_of<P_F32>(x).load(s, xv);
-#pragma unroll
-    for (int i = 0; i < 24; ++i) xv[i] = fmaf(a, pv[i], xv[i]);
-    spinor_of<P_F32>(x).store(s, xv);
-  }
 #pragma unroll
   for (int i = 0; i < 24; ++i) rv[i] = fmaf(-a, q[i], rv[i]);
   rs.store(s, rv);
@@ -740,6 +734,7 @@ void launch_pack_gauge(const Geom& g, const void* U, int prec, void* out, hipStr
   switch (prec) {
     case P_F64: k_pack_gauge<P_F64><<<grid_of(g), kBlock, 0, s>>>(g, u, out); break;
     case P_F32: k_pack_gauge<P_F32><<<grid_of(g), kBlock, 0, s>>>(g, u, out); break;
+    case P_I8: k_pack_gauge<P_I8><<<grid_of(g), kBlock, 0, s>>>(g, u, out); break;
     case P_BF16: k_pack_gauge<P_BF16><<<grid_of(g), kBlock, 0, s>>>(g, u, out); break;
     default: k_pack_gauge<P_F16><<<grid_of(g), kBlock, 0, s>>>(g, u, out); break;
   }
@@ -750,6 +745,7 @@ static void pack_spinor_io(const Geom& g, const IO* in, SpinorBuf out, hipStream
   switch (out.prec) {
     case P_F64: k_pack_spinor<P_F64, IO><<<grid_of(g), kBlock, 0, s>>>(g, in, out); break;
     case P_F32: k_pack_spinor<P_F32, IO><<<grid_of(g), kBlock, 0, s>>>(g, in, out); break;
+    case P_I8: k_pack_spinor<P_I8, IO><<<grid_of(g), kBlock, 0, s>>>(g, in, out); break;
     case P_BF16: k_pack_spinor<P_BF16, IO><<<grid_of(g), kBlock, 0, s>>>(g, in, out); break;
     default: k_pack_spinor<P_F16, IO><<<grid_of(g), kBlock, 0, s>>>(g, in, out); break;
   }
@@ -765,6 +761,7 @@ static void unpack_spinor_io(const Geom& g, SpinorBuf in, IO* out, hipStream_t s
   switch (in.prec) {
     case P_F64: k_unpack_spinor<P_F64, IO><<<grid_of(g), kBlock, 0, s>>>(g, in, out); break;
     case P_F32: k_unpack_spinor<P_F32, IO><<<grid_of(g), kBlock, 0, s>>>(g, in, out); break;
+    case P_I8: k_unpack_spinor<P_I8, IO><<<grid_of(g), kBlock, 0, s>>>(g, in, out); break;
     case P_BF16: k_unpack_spinor<P_BF16, IO><<<grid_of(g), kBlock, 0, s>>>(g, in, out); break;
     default: k_unpack_spinor<P_F16, IO><<<grid_of(g), kBlock, 0, s>>>(g, in, out); break;
   }
@@ -780,6 +777,7 @@ static void convert_from(const Geom& g, SpinorBuf in, SpinorBuf out, int gate, S
   switch (out.prec) {
     case P_F64: k_convert<PA, P_F64><<<grid_of(g), kBlock, 0, s>>>(g, in, out, gate, st); break;
     case P_F32: k_convert<PA, P_F32><<<grid_of(g), kBlock, 0, s>>>(g, in, out, gate, st); break;
+    case P_I8: k_convert<PA, P_I8><<<grid_of(g), kBlock, 0, s>>>(g, in, out, gate, st); break;
     case P_BF16: k_convert<PA, P_BF16><<<grid_of(g), kBlock, 0, s>>>(g, in, out, gate, st); break;
     default: k_convert<PA, P_F16><<<grid_of(g), kBlock, 0, s>>>(g, in, out, gate, st); break;
   }
@@ -789,6 +787,7 @@ void launch_convert(const Geom& g, SpinorBuf in, SpinorBuf out, int gate, Solver
   switch (in.prec) {
     case P_F64: convert_from<P_F64>(g, in, out, gate, st, s); break;
     case P_F32: convert_from<P_F32>(g, in, out, gate, st, s); break;
+    case P_I8: convert_from<P_I8>(g, in, out, gate, st, s); break;
     case P_BF16: convert_from<P_BF16>(g, in, out, gate, st, s); break;
     default: convert_from<P_F16>(g, in, out, gate, st, s); break;
   }
@@ -798,6 +797,7 @@ void launch_zero(const Geom& g, SpinorBuf v, int gate, SolverState* st, hipStrea
   switch (v.prec) {
     case P_F64: k_zero<P_F64><<<grid_of(g), kBlock, 0, s>>>(g, v, gate, st); break;
     case P_F32: k_zero<P_F32><<<grid_of(g), kBlock, 0, s>>>(g, v, gate, st); break;
+    case P_I8: k_zero<P_I8><<<grid_of(g), kBlock, 0, s>>>(g, v, gate, st); break;
     case P_BF16: k_zero<P_BF16><<<grid_of(g), kBlock, 0, s>>>(g, v, gate, st); break;
     default: k_zero<P_F16><<<grid_of(g), kBlock, 0, s>>>(g, v, gate, st); break;
   }
@@ -830,7 +830,7 @@ static void wilson_packed_p(const Geom& g, const void* U, SpinorBuf in, SpinorBu
                             const EventPair* ev, int rows2, RingBuf ring) {
   const double d = mass + 4.0;
   bool done = false;
-  if constexpr (P == P_BF16 || P == P_F16) {
+  if constexpr (P == P_BF16 || P == P_F16 || P == P_I8) {
     if (g.tiled) {
       if (rows2 && dagger) launch(k_wilson_tiled<P, true, true>, g, s, ev, g, U, in, out, d, gate, fin, st, partials, ring);
       else if (rows2) launch(k_wilson_tiled<P, true, false>, g, s, ev, g, U, in, out, d, gate, fin, st, partials, ring);
@@ -861,6 +861,7 @@ void launch_wilson_packed(const Geom& g, int prec, const void* U, SpinorBuf in, 
   switch (prec) {
     case P_F64: wilson_packed_p<P_F64>(g, U, in, out, mass, dagger, gate, fin, st, partials, s, ev, 0, rg); break;
     case P_F32: wilson_packed_p<P_F32>(g, U, in, out, mass, dagger, gate, fin, st, partials, s, ev, 0, rg); break;
+    case P_I8: wilson_packed_p<P_I8>(g, U, in, out, mass, dagger, gate, fin, st, partials, s, ev, rows2, rg); break;
     case P_BF16: wilson_packed_p<P_BF16>(g, U, in, out, mass, dagger, gate, fin, st, partials, s, ev, rows2, rg); break;
     default: wilson_packed_p<P_F16>(g, U, in, out, mass, dagger, gate, fin, st, partials, s, ev, rows2, rg); break;
   }
@@ -869,6 +870,7 @@ void launch_wilson_packed(const Geom& g, int prec, const void* U, SpinorBuf in, 
 void launch_pack_gauge_rows2(const Geom& g, const void* U, int prec, void* out, hipStream_t s) {
   const double2* u = static_cast<const double2*>(U);
   if (prec == P_BF16) k_pack_gauge_rows2<P_BF16><<<grid_of(g), kBlock, 0, s>>>(g, u, static_cast<uint32_t*>(out));
+  else if (prec == P_I8) k_pack_gauge_rows2<P_I8><<<grid_of(g), kBlock, 0, s>>>(g, u, static_cast<uint32_t*>(out));
   else k_pack_gauge_rows2<P_F16><<<grid_of(g), kBlock, 0, s>>>(g, u, static_cast<uint32_t*>(out));
 }
 
@@ -889,15 +891,7 @@ void launch_cg_update(const Geom& g, int prec, const void* U, SpinorBuf t, Spino
       if (g.tiled) launch(k_cg_update<P_F32, P_F32, true, true>, g, s, ev, g, U, t, r, p, x, diag, st, partials);
       else launch(k_cg_update<P_F32, P_F32, false, true>, g, s, ev, g, U, t, r, p, x, diag, st, partials);
       break;
-    case P_BF16:
-      if (g.tiled && rows2) launch(k_cg_update_tiled<P_BF16, true, true>, g, s, ev, g, U, t, r, p, x, diag, st, partials);
-      else if (g.tiled) launch(k_cg_update_tiled<P_BF16, false, true>, g, s, ev, g, U, t, r, p, x, diag, st, partials);
-      else launch(k_cg_update<P_BF16, P_F32, false, true>, g, s, ev, g, U, t, r, p, x, diag, st, partials);
-      break;
-    default:
-      if (g.tiled && rows2) launch(k_cg_update_tiled<P_F16, true, true>, g, s, ev, g, U, t, r, p, x, diag, st, partials);
-      else if (g.tiled) launch(k_cg_update_tiled<P_F16, false, true>, g, s, ev, g, U, t, r, p, x, diag, st, partials);
-      else launch(k_cg_update<P_F16, P_F32, false, true>, g, s, ev, g, U, t, r, p, x, diag, st, partials);
+    default:   // the narrow storage formats use launch_r_update
       break;
   }
   launch_finalize(g, partials, st, F_BETA, G_ITER, s);
@@ -908,10 +902,10 @@ template <int P>
 static void r_update_p(const Geom& g, const void* U, SpinorBuf t, SpinorBuf r, double diag, SolverState* st,
                        double* partials, hipStream_t s, const EventPair* ev, int rows2) {
   const SpinorBuf none{nullptr, nullptr, P};
-  if constexpr (P == P_BF16 || P == P_F16) {
+  if constexpr (P == P_BF16 || P == P_F16 || P == P_I8) {
     if (g.tiled) {
-      if (rows2) launch(k_cg_update_tiled<P, true, false>, g, s, ev, g, U, t, r, none, none, diag, st, partials);
-      else launch(k_cg_update_tiled<P, false, false>, g, s, ev, g, U, t, r, none, none, diag, st, partials);
+      if (rows2) launch(k_cg_update_tiled<P, true>, g, s, ev, g, U, t, r, diag, st, partials);
+      else launch(k_cg_update_tiled<P, false>, g, s, ev, g, U, t, r, diag, st, partials);
       return;
     }
     launch(k_cg_update<P, P_F32, false, false>, g, s, ev, g, U, t, r, none, none, diag, st, partials);
@@ -927,6 +921,7 @@ void launch_r_update(const Geom& g, int prec, const void* U, SpinorBuf t, Spinor
   switch (prec) {
     case P_F64: r_update_p<P_F64>(g, U, t, r, diag, st, partials, s, ev, 0); break;
     case P_F32: r_update_p<P_F32>(g, U, t, r, diag, st, partials, s, ev, 0); break;
+    case P_I8: r_update_p<P_I8>(g, U, t, r, diag, st, partials, s, ev, rows2); break;
     case P_BF16: r_update_p<P_BF16>(g, U, t, r, diag, st, partials, s, ev, rows2); break;
     default: r_update_p<P_F16>(g, U, t, r, diag, st, partials, s, ev, rows2); break;
   }
@@ -939,6 +934,7 @@ void launch_p_update_ring(const Geom& g, SpinorBuf r, const RingBuf& ring, Solve
   switch (ring.prec) {
     case P_F64: launch(k_p_update_ring<P_F64>, g, s, ev, g, r, ring, cst); break;
     case P_F32: launch(k_p_update_ring<P_F32>, g, s, ev, g, r, ring, cst); break;
+    case P_I8: launch(k_p_update_ring<P_I8>, g, s, ev, g, r, ring, cst); break;
     case P_BF16: launch(k_p_update_ring<P_BF16>, g, s, ev, g, r, ring, cst); break;
     default: launch(k_p_update_ring<P_F16>, g, s, ev, g, r, ring, cst); break;
   }
@@ -950,6 +946,7 @@ void launch_accumulate_ring(const Geom& g, SpinorBuf x64, const RingBuf& ring, i
   switch (ring.prec) {
     case P_F64: launch(k_accumulate_ring<P_F64>, g, s, nullptr, g, x64, ring, gate, cst); break;
     case P_F32: launch(k_accumulate_ring<P_F32>, g, s, nullptr, g, x64, ring, gate, cst); break;
+    case P_I8: launch(k_accumulate_ring<P_I8>, g, s, nullptr, g, x64, ring, gate, cst); break;
     case P_BF16: launch(k_accumulate_ring<P_BF16>, g, s, nullptr, g, x64, ring, gate, cst); break;
     default: launch(k_accumulate_ring<P_F16>, g, s, nullptr, g, x64, ring, gate, cst); break;
   }
@@ -968,6 +965,7 @@ void launch_residual(const Geom& g, const void* U64, SpinorBuf t64, SpinorBuf b6
     switch (out.prec) {
       case P_F64: launch(k_residual<P_F64, true>, g, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
       case P_F32: launch(k_residual<P_F32, true>, g, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
+      case P_I8: launch(k_residual<P_I8, true>, g, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
       case P_BF16: launch(k_residual<P_BF16, true>, g, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
       default: launch(k_residual<P_F16, true>, g, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
     }
@@ -975,6 +973,7 @@ void launch_residual(const Geom& g, const void* U64, SpinorBuf t64, SpinorBuf b6
     switch (out.prec) {
       case P_F64: launch(k_residual<P_F64, false>, g, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
       case P_F32: launch(k_residual<P_F32, false>, g, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
+      case P_I8: launch(k_residual<P_I8, false>, g, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
       case P_BF16: launch(k_residual<P_BF16, false>, g, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
       default: launch(k_residual<P_F16, false>, g, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
     }
@@ -987,6 +986,7 @@ void launch_p_update(const Geom& g, SpinorBuf r, SpinorBuf p, SolverState* st, h
   switch (p.prec) {
     case P_F64: launch(k_p_update<P_F64>, g, s, ev, g, r, p, cst); break;
     case P_F32: launch(k_p_update<P_F32>, g, s, ev, g, r, p, cst); break;
+    case P_I8: launch(k_p_update<P_I8>, g, s, ev, g, r, p, cst); break;
     case P_BF16: launch(k_p_update<P_BF16>, g, s, ev, g, r, p, cst); break;
     default: launch(k_p_update<P_F16>, g, s, ev, g, r, p, cst); break;
   }
@@ -1001,6 +1001,7 @@ void launch_norm2(const Geom& g, SpinorBuf v, int gate, int fin, SolverState* st
   switch (v.prec) {
     case P_F64: k_norm2<P_F64><<<grid_of(g), kBlock, 0, s>>>(g, v, gate, fin, st, partials); break;
     case P_F32: k_norm2<P_F32><<<grid_of(g), kBlock, 0, s>>>(g, v, gate, fin, st, partials); break;
+    case P_I8: k_norm2<P_I8><<<grid_of(g), kBlock, 0, s>>>(g, v, gate, fin, st, partials); break;
     case P_BF16: k_norm2<P_BF16><<<grid_of(g), kBlock, 0, s>>>(g, v, gate, fin, st, partials); break;
     default: k_norm2<P_F16><<<grid_of(g), kBlock, 0, s>>>(g, v, gate, fin, st, partials); break;
   }

@@ -39,7 +39,7 @@ __device__ __forceinline__ int face_insert(int f, int mu, int v) {
 
 template <int P>
 struct TileLds {
-  uint4 w[3][kTileSlots];
+  typename SpinorWord<P>::T w[3][kTileSlots];
   float scale[kTileSlots];
 };
 
@@ -59,7 +59,7 @@ __device__ __forceinline__ void tile_stage(const Geom& g, int T, const void* Uv,
   const int l = threadIdx.x;
   const int s = T * kTileSites + l;
   const uint32_t* U = static_cast<const uint32_t*>(Uv);
-  const uint4* src = static_cast<const uint4*>(in.data);
+  const typename SpinorWord<P>::T* src = static_cast<const typename SpinorWord<P>::T*>(in.data);
   const Nbrs nb = neighbours(g, s);
 #pragma unroll
   for (int mu = 0; mu < 4; ++mu)
@@ -71,7 +71,7 @@ __device__ __forceinline__ void tile_stage(const Geom& g, int T, const void* Uv,
     for (int e = 0; e < NE; ++e) lk[4 + mu][e] = U[word_index(nb.bwd[mu], NW, mu * NE + e)];
 #pragma unroll
   for (int w = 0; w < 3; ++w) lds.w[w][l] = src[word_index(s, 3, w)];
-  if constexpr (P == P_F16) lds.scale[l] = in.scale[s];
+  if constexpr (kScaled<P>) lds.scale[l] = in.scale[s];
   // halo: wavefront mu stages the two mu faces
   const int mu = l >> 6;
   const int f = l & 63;
@@ -86,7 +86,7 @@ __device__ __forceinline__ void tile_stage(const Geom& g, int T, const void* Uv,
     lds.w[w][slot_p] = src[word_index(sp, 3, w)];
     lds.w[w][slot_m] = src[word_index(sm, 3, w)];
   }
-  if constexpr (P == P_F16) {
+  if constexpr (kScaled<P>) {
     lds.scale[slot_p] = in.scale[sp];
     lds.scale[slot_m] = in.scale[sm];
   }
@@ -150,10 +150,10 @@ __device__ __forceinline__ TileSrc<P> stage_own_tile(const SpinorBuf& in, int T,
 
 template <int P>
 __device__ __forceinline__ void tile_spinor(const TileLds<P>& lds, int slot, float v[24]) {
-  uint4 d[3];
+  typename SpinorWord<P>::T d[3];
 #pragma unroll
   for (int w = 0; w < 3; ++w) d[w] = lds.w[w][slot];
-  PackedSpinor<P>::unpack(d, P == P_F16 ? lds.scale[slot] : 1.0f, v);
+  PackedSpinor<P>::unpack(d, kScaled<P> ? lds.scale[slot] : 1.0f, v);
 }
 
 // Unpack a prefetched link at its point of use. The empty asm makes each raw

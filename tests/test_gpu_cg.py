@@ -30,7 +30,7 @@ def _true_res(U, x, b, mass, rhs="source"):
     return oracle.true_relative_residual(U, x, b, mass, rhs=rhs)
 
 
-@pytest.mark.parametrize("inner", ["f64", "f32", "bf16", "f16"])
+@pytest.mark.parametrize("inner", ["f64", "f32", "bf16", "f16", "i8"])
 def test_config0_solve(inner):
     log(f"cg c0 inner={inner}")
     U, b = _fields(C0["dims"], C0["kind"], C0["seed"])
@@ -64,7 +64,7 @@ def test_dense_solve_2x2x2x2_and_normal_mode():
         assert rel(to_np(x), xd) <= 1e-9
 
 
-@pytest.mark.parametrize("inner", ["f64", "f32"])
+@pytest.mark.parametrize("inner", ["f64", "f32", "f16", "i8"])
 def test_odd_lattice(inner):
     dims = (5, 3, 7, 4)
     U, b = _fields(dims, "near_identity", 61)
@@ -82,7 +82,7 @@ def test_config1_fp64_16x16x16x32():
     assert res <= TOL * (1 + 1e-3)
 
 
-@pytest.mark.parametrize("inner", ["f32", "bf16", "f16"])
+@pytest.mark.parametrize("inner", ["f32", "bf16", "f16", "i8"])
 def test_mixed_8x8x8x16(inner):
     dims = (8, 8, 8, 16)
     log(f"cg mixed 8^3x16 {inner}")
@@ -198,7 +198,7 @@ def test_iterative_refinement(inner):
 
 
 @pytest.mark.parametrize("inner,ring_len,interval", [("f16", 8, 100), ("f16", 256, 50), ("f32", 8, 50),
-                                                     ("bf16", 12, 1000)])
+                                                     ("bf16", 12, 1000), ("i8", 8, 50)])
 def test_mixed_ring_lengths(inner, ring_len, interval):
     """A mixed solve keeps each iteration's search direction in a ring and
     folds sum_j alpha_j p_j into the FP64 x at reliable updates, or as soon as

@@ -50,7 +50,7 @@ def test_pack_roundtrip_exact_fp64():
     assert np.array_equal(back, psi)
 
 
-@pytest.mark.parametrize("prec,bound", [("f32", 1e-6), ("bf16", 8e-3), ("f16", 1.5e-3)])
+@pytest.mark.parametrize("prec,bound", [("f32", 1e-6), ("bf16", 8e-3), ("f16", 1.5e-3), ("i8", 1e-2)])
 def test_pack_roundtrip_low_precision(prec, bound):
     dims = (5, 3, 7, 4)
     psi = fieldgen.gaussian_spinor(dims, 3)
@@ -58,7 +58,7 @@ def test_pack_roundtrip_low_precision(prec, bound):
     assert rel(back, psi) <= bound
 
 
-@pytest.mark.parametrize("prec,bound", [("f32", 2e-6), ("bf16", 1.5e-2), ("f16", 3e-3)])
+@pytest.mark.parametrize("prec,bound", [("f32", 2e-6), ("bf16", 1.5e-2), ("f16", 3e-3), ("i8", 2e-2)])
 @pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 8, 2)])
 def test_wilson_apply_packed_low_precision(dims, prec, bound):
     log(f"wilson_apply_packed {prec} dims={dims}")
@@ -71,6 +71,30 @@ def test_wilson_apply_packed_low_precision(dims, prec, bound):
     wd.wilson_apply_packed(Up, pin, pout, dims, 0.1, prec, False)
     out = to_np(wd.unpack_spinor(pout, dims, prec))
     assert rel(out, oracle.wilson_D(U, psi, 0.1)) <= bound
+
+
+def test_int8_storage_exact_on_its_grid():
+    """int8 storage keeps v = (b - 128) m / 127 with m the site's largest
+    |component|: spinors whose components are integer multiples of m / 127 come
+    back up to FP32 rounding of the scale (the grid point itself is kept); a
+    site of zeros stays zero; other values round to the nearest grid point
+    (error at most m / 254 per component)."""
+    dims = (4, 4, 4, 4)
+    rng = np.random.default_rng(7)
+    shape = fieldgen.lattice_shape(dims) + (4, 3)
+    m = 2.0 ** rng.integers(-6, 6, size=fieldgen.lattice_shape(dims))[..., None, None]
+    q = rng.integers(-127, 128, size=shape) + 1j * rng.integers(-127, 128, size=shape)
+    q[..., 0, 0] = 127 + 1j * q[..., 0, 0].imag      # the largest |component| is m exactly
+    psi = q * (m / 127.0)
+    psi[0, 0, 0, 0] = 0.0
+    back = to_np(wd.unpack_spinor(wd.pack_spinor(to_dev(psi), "i8"), dims, "i8"))
+    assert (np.abs(back - psi) <= 1e-6 * m).all()
+    assert (back[0, 0, 0, 0] == 0).all()
+    g = fieldgen.gaussian_spinor(dims, 8)
+    back = to_np(wd.unpack_spinor(wd.pack_spinor(to_dev(g), "i8"), dims, "i8"))
+    site_max = np.maximum(np.abs(g.real), np.abs(g.imag)).max(axis=(-2, -1), keepdims=True)
+    err = np.maximum(np.abs((back - g).real), np.abs((back - g).imag))
+    assert (err <= site_max / 254 * (1 + 1e-5)).all()
 
 
 def test_full_size_sampled_sites_32x32x32x64():
@@ -98,7 +122,7 @@ def test_adjoint_identity_on_gpu():
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
 
 
-@pytest.mark.parametrize("prec,bound", [("bf16_rows2", 1.5e-2), ("f16_rows2", 3e-3)])
+@pytest.mark.parametrize("prec,bound", [("bf16_rows2", 1.5e-2), ("f16_rows2", 3e-3), ("i8_rows2", 2e-2)])
 @pytest.mark.parametrize("dims", [(4, 4, 4, 4), (8, 4, 4, 8)])
 def test_two_row_links_parity(dims, prec, bound):
     # SU(3) links stored as two rows, the third rebuilt on the fly
