@@ -230,9 +230,8 @@ __device__ __forceinline__ int fix16(float v) {
 __device__ __forceinline__ uint32_t pack_i16x2(float lo, float hi) {
   return ((uint32_t)fix16(lo) & 0xffffu) | ((uint32_t)fix16(hi) << 16);
 }
-__device__ __forceinline__ float i16_bits2f(uint32_t b) {
-  return (float)(int)(int16_t)(uint16_t)(b & 0xffffu) * (1.0f / kLinkFix);
-}
+__device__ __forceinline__ float i16_raw2f(uint32_t b) { return (float)(int)(int16_t)(uint16_t)(b & 0xffffu); }
+__device__ __forceinline__ float i16_bits2f(uint32_t b) { return i16_raw2f(b) * (1.0f / kLinkFix); }
 
 __device__ __forceinline__ size_t word_index(int s, int nwords, int w) {
   return ((size_t)(s >> 6) * nwords + w) * kSiteBlock + (s & 63);
@@ -286,6 +285,8 @@ template <> struct PackedSpinor<P_BF16> {
   static constexpr bool kFence = false;
   uint4* data;
   float* scale;
+  static __device__ __forceinline__ float raw_factor(float) { return 1.0f; }
+  static __device__ __forceinline__ void unpack_raw(const uint4 d[3], Real v[24]) { unpack(d, 1.0f, v); }
   static __device__ __forceinline__ void unpack(const uint4 d[3], float, Real v[24]) {
 #pragma unroll
     for (int w = 0; w < 3; ++w) {
@@ -332,6 +333,18 @@ template <> struct PackedSpinor<P_F16> {
   static constexpr bool kFence = false;
   uint4* data;
   float* scale;   // per-site magnitude: stored value = v / scale, |stored| <= 1
+  static __device__ __forceinline__ float raw_factor(float sc) { return sc; }
+  static __device__ __forceinline__ void unpack_raw(const uint4 d[3], Real v[24]) {
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+      const uint32_t u[4] = {d[w].x, d[w].y, d[w].z, d[w].w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        v[8 * w + 2 * k] = h_bits2f(u[k]);
+        v[8 * w + 2 * k + 1] = h_bits2f(u[k] >> 16);
+      }
+    }
+  }
   static __device__ __forceinline__ void unpack(const uint4 d[3], float sc, Real v[24]) {
 #pragma unroll
     for (int w = 0; w < 3; ++w) {
@@ -379,26 +392,33 @@ template <> struct PackedSpinor<P_F16> {
   }
 };
 
-// int8 storage: value = (b - 128) * scale / 127 for the stored byte b
-// (offset binary, b in 1..255), scale = the site's largest |component|, so
-// unpacking a value is one byte-to-float convert and one FMA. A site with a
-// NaN or Inf component gets a NaN scale (it stays NaN when read back).
+// int8 storage: value = q * scale / 127 for the stored signed byte q
+// (-127..127), scale = the site's largest |component|. Converting a byte is one
+// sign-extending convert; the factor scale / 127 can be applied after the
+// linear algebra (raw_factor). A site with a NaN or Inf component gets a NaN
+// scale (it stays NaN when read back).
 template <> struct PackedSpinor<P_I8> {
   using Real = float;
   static constexpr bool kFence = false;
   uint2* data;
   float* scale;
-  static __device__ __forceinline__ void unpack(const uint2 d[3], float sc, Real v[24]) {
-    const float f = sc * (1.0f / 127.0f);
-    const float off = -128.0f * f;
+  static __device__ __forceinline__ float raw_factor(float sc) { return sc * (1.0f / 127.0f); }
+  static __device__ __forceinline__ void unpack_raw(const uint2 d[3], Real v[24]) {
 #pragma unroll
     for (int w = 0; w < 3; ++w) {
       const uint32_t u[2] = {d[w].x, d[w].y};
 #pragma unroll
       for (int k = 0; k < 2; ++k)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) v[8 * w + 4 * k + b] = fmaf((float)((u[k] >> (8 * b)) & 0xffu), f, off);
+        for (int b = 0; b < 4; ++b)
+          v[8 * w + 4 * k + b] = (float)(int)(int8_t)(uint8_t)((u[k] >> (8 * b)) & 0xffu);
     }
+  }
+  static __device__ __forceinline__ void unpack(const uint2 d[3], float sc, Real v[24]) {
+    unpack_raw(d, v);
+    const float f = raw_factor(sc);
+#pragma unroll
+    for (int i = 0; i < 24; ++i) v[i] *= f;
   }
   static __device__ __forceinline__ void pack(const Real v[24], uint2 d[3], float& sc) {
     float m = 0.f, chk = 0.f;
@@ -417,7 +437,7 @@ template <> struct PackedSpinor<P_I8> {
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
           const int q = (int)rintf(fminf(fmaxf(v[8 * w + 4 * k + b] * inv, -127.f), 127.f));
-          u[k] |= (uint32_t)(q + 128) << (8 * b);
+          u[k] |= ((uint32_t)q & 0xffu) << (8 * b);
         }
       d[w] = make_uint2(u[0], u[1]);
     }

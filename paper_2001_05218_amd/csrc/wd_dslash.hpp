@@ -78,6 +78,29 @@ __device__ __forceinline__ void reconstruct_add(R acc[24], const R w[12]) {
   }
 }
 
+// acc += f * (reconstruction of w): reconstruct_add with every term scaled by
+// f, the FMA taking the place of the add (f carries the storage scales that
+// the raw unpacking left out).
+template <int MU, int S, typename R>
+__device__ __forceinline__ void reconstruct_fma(R acc[24], const R w[12], R f) {
+  using T = SpinTab<MU>;
+  constexpr int sh = (S > 0) ? 0 : 2;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    acc[(0 * 3 + c) * 2] = fma(f, w[(0 * 3 + c) * 2], acc[(0 * 3 + c) * 2]);
+    acc[(0 * 3 + c) * 2 + 1] = fma(f, w[(0 * 3 + c) * 2 + 1], acc[(0 * 3 + c) * 2 + 1]);
+    acc[(1 * 3 + c) * 2] = fma(f, w[(1 * 3 + c) * 2], acc[(1 * 3 + c) * 2]);
+    acc[(1 * 3 + c) * 2 + 1] = fma(f, w[(1 * 3 + c) * 2 + 1], acc[(1 * 3 + c) * 2 + 1]);
+    R a, b;
+    ipow<4 - T::n0 + sh>(w[(0 * 3 + c) * 2], w[(0 * 3 + c) * 2 + 1], a, b);
+    acc[((2 + T::p0) * 3 + c) * 2] = fma(f, a, acc[((2 + T::p0) * 3 + c) * 2]);
+    acc[((2 + T::p0) * 3 + c) * 2 + 1] = fma(f, b, acc[((2 + T::p0) * 3 + c) * 2 + 1]);
+    ipow<4 - T::n1 + sh>(w[(1 * 3 + c) * 2], w[(1 * 3 + c) * 2 + 1], a, b);
+    acc[((2 + T::p1) * 3 + c) * 2] = fma(f, a, acc[((2 + T::p1) * 3 + c) * 2]);
+    acc[((2 + T::p1) * 3 + c) * 2 + 1] = fma(f, b, acc[((2 + T::p1) * 3 + c) * 2 + 1]);
+  }
+}
+
 // Row 2 of an SU(3) matrix from rows 0 and 1: u2_k = conj(u0_i u1_j - u0_j u1_i),
 // (i, j, k) cyclic (unitarity with unit determinant).
 template <typename R>

@@ -441,8 +441,11 @@ __global__ __launch_bounds__(kBlock) WD_TILED_OCCUPANCY void k_cg_update_tiled(G
   rs.load(s, rv);
 #pragma unroll
   for (int i = 0; i < 24; ++i) rv[i] = fmaf(-a, q[i], rv[i]);
-  rs.store(s, rv);
-  rs.load(s, rv);   // the norm of what the next iteration reads
+  typename SpinorWord<P>::T d[3];
+  float sc;
+  PackedSpinor<P>::pack(rv, d, sc);
+  rs.store_raw(s, d, sc);
+  PackedSpinor<P>::unpack(d, sc, rv);   // the norm of what the next iteration reads
   double n2 = 0.0;
 #pragma unroll
   for (int i = 0; i < 24; ++i) n2 += (double)rv[i] * (double)rv[i];

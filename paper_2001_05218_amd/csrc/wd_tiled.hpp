@@ -156,9 +156,27 @@ __device__ __forceinline__ void tile_spinor(const TileLds<P>& lds, int slot, flo
   PackedSpinor<P>::unpack(d, kScaled<P> ? lds.scale[slot] : 1.0f, v);
 }
 
+// The stored numbers of a staged spinor without its per-site factor, and the
+// factor (value = f * raw): the hops apply f once, after the link multiply.
+template <int P>
+__device__ __forceinline__ float tile_spinor_raw(const TileLds<P>& lds, int slot, float v[24]) {
+  typename SpinorWord<P>::T d[3];
+#pragma unroll
+  for (int w = 0; w < 3; ++w) d[w] = lds.w[w][slot];
+  PackedSpinor<P>::unpack_raw(d, v);
+  return PackedSpinor<P>::raw_factor(kScaled<P> ? lds.scale[slot] : 1.0f);
+}
+
+// Links as link_from returns them are the true links divided by kLinkUnit<P>
+// (int16 fixed point is left unscaled until the hop factor).
+template <int P> constexpr float kLinkUnit = (P == P_I8) ? 1.0f / kLinkFix : 1.0f;
+
 // Unpack a prefetched link at its point of use. The empty asm makes each raw
 // word opaque here, so the compiler cannot unpack all eight links right after
 // their loads (which would keep 144 floats live instead of 72 raw words).
+// For int16 fixed point the entries come back in units of 1 / kLinkFix (the
+// hop multiplies by kLinkUnit<P> once); the rebuilt row 2 is brought to the
+// same units.
 template <int P, bool C12>
 __device__ __forceinline__ void link_from(const uint32_t raw[9], float u[18]) {
   constexpr int NE = LinkFormat<C12>::entries;
@@ -166,9 +184,20 @@ __device__ __forceinline__ void link_from(const uint32_t raw[9], float u[18]) {
   for (int e = 0; e < NE; ++e) {
     uint32_t r = raw[e];
     asm volatile("" : "+v"(r));
-    unpack_link16<P>(r, u[2 * e], u[2 * e + 1]);
+    if constexpr (P == P_I8) {
+      u[2 * e] = i16_raw2f(r);
+      u[2 * e + 1] = i16_raw2f(r >> 16);
+    } else {
+      unpack_link16<P>(r, u[2 * e], u[2 * e + 1]);
+    }
   }
-  if constexpr (C12) su3_third_row(u);
+  if constexpr (C12) {
+    su3_third_row(u);
+    if constexpr (P == P_I8) {
+#pragma unroll
+      for (int i = 12; i < 18; ++i) u[i] *= 1.0f / kLinkFix;
+    }
+  }
 }
 
 template <int P, bool C12, int MU, bool DAG>
@@ -181,16 +210,16 @@ __device__ __forceinline__ void tile_hop(const TileLds<P>& lds, const uint32_t l
   const int slot_f = (lm < 3) ? l + ls : kTileSites + (2 * MU) * 64 + fp;
   const int slot_b = (lm > 0) ? l - ls : kTileSites + (2 * MU + 1) * 64 + fp;
   float psi[24], h[12], w[12], u[18];
-  tile_spinor<P>(lds, slot_f, psi);
+  float f = tile_spinor_raw<P>(lds, slot_f, psi) * kLinkUnit<P>;
   link_from<P, C12>(lk[MU], u);
   project<MU, SF>(psi, h);
   su3_mul_half<false>(u, h, w);
-  reconstruct_add<MU, SF>(acc, w);
-  tile_spinor<P>(lds, slot_b, psi);
+  reconstruct_fma<MU, SF>(acc, w, f);
+  f = tile_spinor_raw<P>(lds, slot_b, psi) * kLinkUnit<P>;
   link_from<P, C12>(lk[4 + MU], u);
   project<MU, SB>(psi, h);
   su3_mul_half<true>(u, h, w);
-  reconstruct_add<MU, SB>(acc, w);
+  reconstruct_fma<MU, SB>(acc, w, f);
   // keep the scheduler from hoisting the next hop's LDS reads and unpacking
   // above this one (that multiplies the live registers for 16-bit data)
   __builtin_amdgcn_sched_barrier(0);
@@ -209,9 +238,9 @@ __device__ __forceinline__ void tile_wilson(const TileLds<P>& lds, const uint32_
   tile_hop<P, C12, 2, DAG>(lds, lk, l, acc);
   tile_hop<P, C12, 3, DAG>(lds, lk, l, acc);
   float c[24];
-  tile_spinor<P>(lds, l, c);
+  const float dc = diag * tile_spinor_raw<P>(lds, l, c);
 #pragma unroll
-  for (int i = 0; i < 24; ++i) out[i] = fmaf(diag, c[i], -0.5f * acc[i]);
+  for (int i = 0; i < 24; ++i) out[i] = fmaf(dc, c[i], -0.5f * acc[i]);
 }
 
 }  // namespace wd

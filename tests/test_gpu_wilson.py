@@ -74,7 +74,7 @@ def test_wilson_apply_packed_low_precision(dims, prec, bound):
 
 
 def test_int8_storage_exact_on_its_grid():
-    """int8 storage keeps v = (b - 128) m / 127 with m the site's largest
+    """int8 storage keeps v = q m / 127 (q a signed byte) with m the site's largest
     |component|: spinors whose components are integer multiples of m / 127 come
     back up to FP32 rounding of the scale (the grid point itself is kept); a
     site of zeros stays zero; other values round to the nearest grid point
