@@ -120,6 +120,8 @@ def parse():
     ap.add_argument("--dslash-reps", type=int, default=200)
     ap.add_argument("--dims", default=",".join(str(d) for d in DIMS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-other-rows", action="store_true",
+                    help="skip the batched, force and autograd measurements")
     ap.add_argument("--cpu-sample-only", action="store_true", help=argparse.SUPPRESS)
     return ap.parse_args()
 
@@ -171,6 +173,90 @@ def run_cpu_baseline(dims, fp64_iters):
 
 
 # -------------------------------------------------------------------- GPU
+
+# Batched workload (24^3x48, Haar links, m = 0.05, 12 point + 4 Gaussian sources,
+# complex64 I/O): per iteration and site the persistent kernel moves the FP32
+# links twice (D and D^+, 2 x 288 B, shared by all systems) and, per active
+# system, p, t (D), t, r, x-hat, p (D^+ update) and r, p (p update) in FP32.
+BATCHED_DIMS = (24, 24, 24, 48)
+BATCHED_LINK_B = 2 * 288
+BATCHED_RHS_B = 2 * 96 + (96 + 2 * 96 + 2 * 96 + 96) + (96 + 2 * 96)
+# Force G(a, b) in FP64 on canonical fields: a, b in (each once) + 4 x 9 complex out.
+FORCE_BYTES = 2 * 192 + 4 * 9 * 16
+
+
+def bench_batched(dev):
+    import torch
+    import fieldgen
+    import paper_2001_05218_amd as wd
+    dims = BATCHED_DIMS
+    V = int(np.prod(dims))
+    U = torch.from_numpy(fieldgen.gauge_field(dims, "haar", 200105248)).to(dev)
+    pts = fieldgen.point_sources(dims)[:12]
+    gs = fieldgen.gaussian_spinor(dims, 200105249, nrhs=4)
+    B = torch.from_numpy(np.concatenate([pts, gs]).astype(np.complex64)).to(dev)
+    p, _ = wd.ops.make_params(TOL, 20000, "f32", 50, "source", wd._lib.WD_C64, True, 0)
+    ws = torch.empty(wd.workspace_bytes(dims, p, 16), dtype=torch.uint8, device=dev)
+    wd.cg_solve_batched(U, B, 0.05, tol=TOL, workspace=ws)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    X, infos = wd.cg_solve_batched(U, B, 0.05, tol=TOL, workspace=ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    its = [i["iterations"] for i in infos]
+    alg = V * (BATCHED_LINK_B * max(its) + BATCHED_RHS_B * sum(its))
+    out = {"seconds": dt, "nrhs": 16, "lattice_xyzt": list(dims), "iterations_max": max(its),
+           "iterations_mean": float(np.mean(its)), "true_rel_res_max": max(i["true_rel_res"] for i in infos),
+           "site_rhs_iterations_per_s": V * sum(its) / dt, "algorithmic_GB_per_s": alg / dt / 1e9,
+           "frac_hbm": alg / dt / 1e9 / HBM_PEAK_GBS}
+    del U, B, X, ws
+    return out
+
+
+def bench_force(dev, a, b, reps=20):
+    """G(a, b) on the benchmark lattice (FP64, canonical layout), HIP events on one stream."""
+    import torch
+    import paper_2001_05218_amd as wd
+    dims = wd.ops.dims_of_spinor(a)
+    V = int(np.prod(dims))
+    stream = torch.cuda.Stream(dev)
+    with torch.cuda.stream(stream):
+        F = wd.wilson_force(a, b)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            wd.wilson_force(a, b, out=F)
+        e1.record(stream)
+        e1.synchronize()
+    avg = e0.elapsed_time(e1) / 1e3 / reps
+    gbs = FORCE_BYTES * V / avg / 1e9
+    del F
+    return {"avg_us": avg * 1e6, "bytes_per_site": FORCE_BYTES, "GB_per_s": gbs, "frac_hbm": gbs / HBM_PEAK_GBS}
+
+
+def bench_autograd(dev):
+    """Differentiable solve on 16^3x32 (links exp(i 0.3 H), m = 0.1): loss = Re phi^+ chi,
+    chi = (D^+D)^{-1} phi; forward + backward (adjoint solve, 2 D, 2 force kernels)."""
+    import torch
+    import fieldgen
+    import paper_2001_05218_amd as wd
+    dims = (16, 16, 16, 32)
+    U = torch.from_numpy(fieldgen.gauge_field(dims, "near_identity", 200105258, eps=0.3)).to(dev)
+    phi = torch.from_numpy(fieldgen.gaussian_spinor(dims, 200105259)).to(dev)
+    times = []
+    for _ in range(3):
+        Ug = U.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        chi = wd.wilson_solve(Ug, phi, 0.1, tol=1e-10)
+        loss = (phi.conj() * chi).real.sum()
+        loss.backward()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+    return {"seconds": min(times), "lattice_xyzt": list(dims), "mass": 0.1, "tol": 1e-10,
+            "note": "forward solve + adjoint solve + 2 D + 2 force kernels, FP64"}
+
 
 def main():
     args = parse()
@@ -317,6 +403,12 @@ def main():
     copy_gbs = 2 * n * 4 / (e0.elapsed_time(e1) / 1e3 / 10) / 1e9
     del src, dst
 
+    other = None
+    if not args.no_other_rows:
+        other = {"force_32x32x32x64": bench_force(dev, bt, x64), "batched_cg": bench_batched(dev),
+                 "autograd_solve": bench_autograd(dev)}
+        log(f"other rows: {other}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, 1 core)")
@@ -371,6 +463,7 @@ def main():
                      "avg_launch_us": kern["avg_us"],
                      "traffic_source": traffic["file"] if traffic else None},
         "loop_kernels": loop,
+        "other_rows": other,
         "copy_ceiling_GB_per_s": copy_gbs,
         "kernel_source_sha": kernel_source_sha(),
         "cpu_baseline": cpu,
