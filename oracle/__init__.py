@@ -14,6 +14,8 @@ Modules
              dense assembly for tiny lattices, site-local evaluation.
   solver  -- conjugate gradient on the normal equations (CGNR), dense solve.
   force   -- derivative of the solve with respect to the gauge links.
+  laplace -- a second operator through the same CG: the gauge-covariant
+             lattice Laplacian on colour vectors, plain CG, dense assembly.
 
 Parity status: every function here is pinned by the ``-m "not gpu"`` tests
 in ``tests/test_oracle_*.py`` against closed forms, invariants and brute
@@ -33,6 +35,7 @@ from .dirac import (
 )
 from .solver import cgnr, dense_solve_normal, true_relative_residual
 from .force import force_G, solve_gradients
+from . import laplace
 
 __all__ = [
     "GAMMA",
@@ -49,4 +52,5 @@ __all__ = [
     "true_relative_residual",
     "force_G",
     "solve_gradients",
+    "laplace",
 ]
