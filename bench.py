@@ -258,6 +258,47 @@ def bench_autograd(dev):
             "note": "forward solve + adjoint solve + 2 D + 2 force kernels, FP64"}
 
 
+# Laplacian CG (FP64) on the benchmark's links: per iteration and site the
+# stencil moves 4 x 9 complex128 links + p in + t out, the vector update
+# t, p, r, x in and r, x out, the p update r, p in and p out (48 B per colour vector).
+LAP_M2 = 0.05
+LAP_BYTES = (576 + 2 * 48, 6 * 48, 3 * 48)
+
+
+def bench_laplace(dev, Ut):
+    """Plain FP64 CG on L x = b, L the gauge-covariant Laplacian (m2 = 0.05) on
+    the benchmark's lattice and links, Gaussian colour source, tol 1e-10."""
+    import torch
+    import fieldgen
+    import paper_2001_05218_amd as wd
+    lt, lz, ly, lx = (int(n) for n in Ut.shape[1:5])
+    dims = (lx, ly, lz, lt)
+    V = int(np.prod(dims))
+    b = torch.from_numpy(fieldgen.gaussian_colour(dims, 200105268)).to(dev)
+    p, _ = wd.ops.make_params(TOL, 20000, "f64", 50, "source", wd._lib.WD_C128, True, 0)
+    ws = torch.empty(wd.laplace_workspace_bytes(dims, p), dtype=torch.uint8, device=dev)
+    _, prof = wd.laplace_cg_solve(Ut, b, LAP_M2, tol=TOL, max_iter=20000, workspace=ws, profile=True)
+    times = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x, info = wd.laplace_cg_solve(Ut, b, LAP_M2, tol=TOL, max_iter=20000, workspace=ws)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+    ks = prof["kernel_seconds"]
+    kern = {}
+    for name, sec, nb in zip(("stencil", "update", "p_update"), ks, LAP_BYTES):
+        gbs = nb * V / sec / 1e9 if sec > 0 else 0.0
+        kern[name] = {"avg_us": sec * 1e6, "bytes_per_site": nb, "GB_per_s": gbs, "frac_hbm": gbs / HBM_PEAK_GBS}
+    it = info["iterations"]
+    alg = sum(LAP_BYTES) * V * it
+    out = {"seconds": min(times), "iterations": it, "true_rel_res": info["true_rel_res"], "m2": LAP_M2,
+           "lattice_xyzt": list(dims), "algorithmic_GB_per_s": alg / min(times) / 1e9,
+           "frac_hbm": alg / min(times) / 1e9 / HBM_PEAK_GBS, "kernels": kern}
+    del b, x, ws
+    return out
+
+
 def main():
     args = parse()
     dims = tuple(int(v) for v in args.dims.split(","))
@@ -345,20 +386,12 @@ def main():
                   "true_rel_res": iref["true_rel_res"], "inner_tol": 0.1}
     log(f"refinement {best}: {refinement}")
 
-    # error of the mixed solution against the FP64 solution and a sampled
-    # oracle residual (the oracle evaluates D^+D x site by site)
+    # error of the mixed solution against the FP64 solution (both GPU solves;
+    # the oracle's sampled check of this workload is a GPU test)
     xm = x.cpu().numpy()
     x64n = x64.cpu().numpy()
     diff = float(np.linalg.norm(xm - x64n) / np.linalg.norm(x64n))
-    import oracle
-    rng = np.random.default_rng(1)
-    sites = [tuple(int(rng.integers(0, L)) for L in dims) for _ in range(8)]
-    Uh = Ut.cpu().numpy()
-    lhs = oracle.normal_op_sites(Uh, xm, MASS, sites)
-    rhs = oracle.wilson_D_sites(Uh, b, MASS, sites, dagger=True)
-    # ||b' - D^+D x|| / ||b'|| restricted to the sampled sites
-    sampled = float(np.linalg.norm(lhs - rhs) / np.linalg.norm(rhs))
-    del Uh
+    del xm, x64n
 
     # Dslash roofline: D^+ in the inner storage precision, HIP events on one stream
     reps = args.dslash_reps
@@ -406,7 +439,7 @@ def main():
     other = None
     if not args.no_other_rows:
         other = {"force_32x32x32x64": bench_force(dev, bt, x64), "batched_cg": bench_batched(dev),
-                 "autograd_solve": bench_autograd(dev)}
+                 "autograd_solve": bench_autograd(dev), "laplace_cg_32x32x32x64": bench_laplace(dev, Ut)}
         log(f"other rows: {other}")
 
     cpu = None
@@ -450,7 +483,7 @@ def main():
         "mixed_cg": {"seconds": per, "iterations": infos[-1]["iterations"],
                      "two_row_links": bool(infos[-1]["two_row_links"]),
                      "reliable_updates": infos[-1]["reliable_updates"], "true_rel_res": infos[-1]["true_rel_res"],
-                     "rel_diff_vs_fp64_solution": diff, "sampled_oracle_residual": sampled},
+                     "rel_diff_vs_fp64_solution": diff},
         "fp64_cg": fp64,
         "refinement_cg": refinement,
         "speedup_mixed_vs_fp64": fp64["seconds"] / per,

@@ -139,6 +139,16 @@ def gaussian_spinor(dims, seed: int, nrhs: int | None = None) -> np.ndarray:
     return (re + 1j * im) / np.sqrt(2.0)
 
 
+def gaussian_colour(dims, seed: int) -> np.ndarray:
+    """Gaussian colour vector field, shape (Lt, Lz, Ly, Lx, 3), every complex
+    component (N(0,1) + i N(0,1)) / sqrt(2)."""
+    shp = lattice_shape(dims) + (3,)
+    rng = np.random.default_rng(seed)
+    re = rng.standard_normal(shp)
+    im = rng.standard_normal(shp)
+    return (re + 1j * im) / np.sqrt(2.0)
+
+
 def point_sources(dims, site=(0, 0, 0, 0)) -> np.ndarray:
     """The 12 point sources delta_{x,site} delta_{spin,s} delta_{colour,c}.
 

@@ -216,6 +216,47 @@ int wd_unpack_spinor(const wd_lattice* lat, const void* in, int32_t prec, void* 
 int wilson_apply_packed(const wd_lattice* lat, double mass, int32_t prec, const void* U_packed,
                         const void* in_packed, void* out_packed, int32_t dagger, void* stream);
 
+/* ---- a second operator through the same solver: the gauge-covariant Laplacian ----
+ *
+ * The paper presents its CG design as a backbone on which other linear
+ * operators can be solved with the data movement unchanged (abstract,
+ * Sec. 3.2, Sec. 7). This operator acts on colour vectors (3 complex numbers
+ * per site) with the same links and the same nearest-neighbour stencil shape,
+ * without spin:
+ *
+ *   (L psi)(x) = (m2 + 8) psi(x) - sum_{mu=0..3} [ U_mu(x) psi(x + mu) + U_mu(x - mu)^+ psi(x - mu) ]
+ *
+ * Hermitian; for unitary links the hopping sum has norm <= 8, so L is positive
+ * definite for m2 > 0 (spectrum in [m2, m2 + 16]) and CG solves L x = b
+ * directly. Colour field layout: (Lt, Lz, Ly, Lx, 3), complex128 (complex64
+ * for solver I/O where params->io_dtype says so). U as above. */
+
+/* out = L psi on canonical complex128 fields (device). Asynchronous on
+ * `stream`; no workspace. Any finite m2 is accepted. */
+int laplace_apply(const wd_lattice* lat, double m2, const void* U, const void* psi, void* out, void* stream);
+
+/* Device workspace of laplace_cg_solve for these parameters, in bytes; 0 on an
+ * invalid argument. */
+size_t laplace_workspace_bytes(const wd_lattice* lat, const wd_cg_params* params);
+
+/*
+ * Solve L x = b by plain FP64 conjugate gradient, on the Wilson solver's
+ * machinery (device-resident state, deterministic reductions, host polling).
+ * Uses params->tol (||b - L x|| / ||b||, confirmed by an FP64 recomputation),
+ * max_iter, io_dtype, zero_guess, history / history_len and profile
+ * (kernel_seconds: (0) t = L p with <p, t>, (1) x += alpha p and r -= alpha t
+ * with ||r||^2, (2) p = r + beta p). inner_prec must be WD_F64; rhs_mode,
+ * scheme, reliable_interval, inner_tol and ring_len are ignored.
+ *   U, b, x, workspace: device, owned by the caller (x: initial guess unless
+ *   zero_guess, solution on return); result: host, may be NULL.
+ * BLOCKS until the solve ends. Returns WD_OK, WD_NOT_CONVERGED (x holds the
+ * last iterate), WD_ERR_BREAKDOWN if <p, L p> <= 0 (L not positive definite),
+ * or another WD_ERR_* code.
+ */
+int laplace_cg_solve(const wd_lattice* lat, double m2, const void* U, const void* b, void* x,
+                     const wd_cg_params* params, wd_cg_result* result, void* workspace, size_t ws_bytes,
+                     void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -34,6 +34,27 @@ def laplace(U: np.ndarray, psi: np.ndarray, m2: float) -> np.ndarray:
     return out
 
 
+def laplace_sites(U: np.ndarray, psi: np.ndarray, m2: float, sites) -> np.ndarray:
+    """(L psi)(x) at the listed sites (x, y, z, t) only, from the definition
+    with explicit periodic neighbour indices; returns (len(sites), 3)."""
+    lt, lz, ly, lx = psi.shape[:4]
+    dims = (lx, ly, lz, lt)
+    out = np.zeros((len(sites), 3), dtype=np.complex128)
+    for k, site in enumerate(sites):
+        c = list(site)
+        x, y, z, t = c
+        acc = (m2 + 8.0) * psi[t, z, y, x]
+        for mu in range(4):
+            f = list(c)
+            f[mu] = (f[mu] + 1) % dims[mu]
+            b = list(c)
+            b[mu] = (b[mu] - 1) % dims[mu]
+            acc = acc - U[mu, t, z, y, x] @ psi[f[3], f[2], f[1], f[0]]
+            acc = acc - U[mu, b[3], b[2], b[1], b[0]].conj().T @ psi[b[3], b[2], b[1], b[0]]
+        out[k] = acc
+    return out
+
+
 def dense_laplace(U: np.ndarray, m2: float, dims) -> np.ndarray:
     """The (3V x 3V) matrix of L, assembled block by block from the formula.
 

@@ -16,5 +16,8 @@ from .ops import (  # noqa: F401
     empty_packed_spinor,
     wilson_apply_packed,
     workspace_bytes,
+    laplace_apply,
+    laplace_cg_solve,
+    laplace_workspace_bytes,
 )
 from .autograd import WilsonSolve, wilson_solve  # noqa: F401

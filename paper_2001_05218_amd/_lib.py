@@ -90,6 +90,9 @@ SIGNATURES = {
     "wd_pack_spinor": (ctypes.c_int, [_LAT, _P, ctypes.c_int32, ctypes.c_int32, _P, _P]),
     "wd_unpack_spinor": (ctypes.c_int, [_LAT, _P, ctypes.c_int32, _P, ctypes.c_int32, _P]),
     "wilson_apply_packed": (ctypes.c_int, [_LAT, ctypes.c_double, ctypes.c_int32, _P, _P, _P, ctypes.c_int32, _P]),
+    "laplace_apply": (ctypes.c_int, [_LAT, ctypes.c_double, _P, _P, _P, _P]),
+    "laplace_workspace_bytes": (ctypes.c_size_t, [_LAT, _PAR]),
+    "laplace_cg_solve": (ctypes.c_int, [_LAT, ctypes.c_double, _P, _P, _P, _PAR, _RES, _P, ctypes.c_size_t, _P]),
 }
 
 _lib = None

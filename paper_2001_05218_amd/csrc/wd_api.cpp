@@ -245,7 +245,7 @@ int fill_result(wd_cg_result* res, const SolverState& st, int code, double secs,
 
 int status_to_code(int status) {
   if (status == 1) return WD_OK;
-  if (status == -3) return fail(WD_ERR_BREAKDOWN, "CG breakdown: <p, D^+D p> <= 0");
+  if (status == -3) return fail(WD_ERR_BREAKDOWN, "CG breakdown: <p, A p> <= 0 (A not positive definite)");
   if (status == -4) return fail(WD_ERR_NAN, "NaN or Inf encountered in a CG reduction");
   if (status == -5) return fail(WD_ERR_HIP, "internal: search-direction ring overflow");
   return WD_OK;
@@ -483,10 +483,10 @@ int next_chunk(const SolverState& s, int enqueued, int max_iter) {
   return std::min(n, left);
 }
 
-int copy_history(const CgWorkspace& w, const wd_cg_params* p, hipStream_t s, int iters) {
+int copy_history(const double* hist, const wd_cg_params* p, hipStream_t s, int iters) {
   if (!p->history || p->history_len <= 0) return WD_OK;
   const int n = std::min(iters, p->history_len);
-  if (n > 0) HIP_TRY(hipMemcpyAsync(p->history, w.hist, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+  if (n > 0) HIP_TRY(hipMemcpyAsync(p->history, hist, sizeof(double) * n, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   for (int i = n; i < p->history_len; ++i) p->history[i] = 0.0;
   return WD_OK;
@@ -579,7 +579,7 @@ int cg_plain(const Geom& g, double mass, const void* U, const void* b, void* x, 
   }
   launch_unpack_spinor(g, w.x64, x, p->io_dtype == WD_C64, s);
   HIP_TRY(hipGetLastError());
-  if ((rc = copy_history(w, p, s, st.iter))) return rc;
+  if ((rc = copy_history(w.hist, p, s, st.iter))) return rc;
   HIP_TRY(hipStreamSynchronize(s));
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (res) clock_read(clk, enqueued, 3, res->kernel_seconds);
@@ -680,7 +680,7 @@ int cg_mixed(const Geom& g, double mass, const void* U, const void* b, void* x, 
   }
   launch_unpack_spinor(g, w.x64, x, p->io_dtype == WD_C64, s);
   HIP_TRY(hipGetLastError());
-  if ((rc = copy_history(w, p, s, st.iter))) return rc;
+  if ((rc = copy_history(w.hist, p, s, st.iter))) return rc;
   HIP_TRY(hipStreamSynchronize(s));
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (res) {
@@ -695,7 +695,157 @@ int cg_mixed(const Geom& g, double mass, const void* U, const void* b, void* x, 
   return fill_result(res, st, code, secs, iter_rel);
 }
 
+// ---- the gauge-covariant Laplacian: the same state, gates, reductions and
+// host loop as cg_plain, with the colour-vector stencil and updates.
+
+struct LapWorkspace {
+  SolverState* st;
+  double* partials;
+  double* hist;
+  void* U64;
+  void *b, *x, *r, *p, *t;   // packed FP64 colour fields
+  size_t bytes;
+};
+
+LapWorkspace layout_lap(void* base, const Geom& g, int hist_len) {
+  Carver c(base);
+  LapWorkspace w{};
+  w.st = static_cast<SolverState*>(c.take(sizeof(SolverState)));
+  w.partials = static_cast<double*>(c.take(sizeof(double) * (size_t)g.nblocks));
+  w.hist = static_cast<double*>(c.take(sizeof(double) * (size_t)(hist_len > 0 ? hist_len : 1)));
+  w.U64 = c.take(gauge_bytes(P_F64, g.Vpad));
+  const size_t vb = (size_t)g.Vpad * 3 * sizeof(double2);
+  w.b = c.take(vb);
+  w.x = c.take(vb);
+  w.r = c.take(vb);
+  w.p = c.take(vb);
+  w.t = c.take(vb);
+  w.bytes = c.off;
+  return w;
+}
+
+int validate_lap_params(const wd_cg_params* p) {
+  int rc = validate_params(p);
+  if (rc) return rc;
+  if (p->inner_prec != WD_F64) return fail(WD_ERR_INVALID, "laplace_cg_solve runs FP64 CG: inner_prec must be WD_F64");
+  return WD_OK;
+}
+
+int lap_cg(const Geom& g, double m2, const void* U, const void* b, void* x, const wd_cg_params* p,
+           wd_cg_result* res, void* ws, hipStream_t s, std::chrono::steady_clock::time_point t0) {
+  const LapWorkspace w = layout_lap(ws, g, p->history_len);
+  const int c64 = p->io_dtype == WD_C64;
+  launch_init_state(w.st, p->tol, 0, 0.0, w.hist, p->history_len, s);
+  launch_pack_gauge(g, U, P_F64, w.U64, s);
+  launch_lap_pack(g, b, c64, w.b, s);
+  launch_lap_norm2(g, w.b, F_BNORM, w.st, w.partials, s);
+  if (p->zero_guess) launch_lap_copy(g, nullptr, w.x, G_ALWAYS, w.st, s);
+  else launch_lap_pack(g, x, c64, w.x, s);
+  launch_lap_residual(g, w.U64, w.x, w.b, w.r, m2, G_ALWAYS, F_RHO_INIT, w.st, w.partials, s);
+  launch_lap_copy(g, w.r, w.p, G_ALWAYS, w.st, s);
+  HIP_TRY(hipGetLastError());
+
+  int rc;
+  HostMirror* m;
+  if ((rc = get_mirror(&m))) return rc;
+  KernelClock* clk = nullptr;
+  if (p->profile && (rc = get_clock(&clk))) return rc;
+  Poller poll{m, nullptr, s};
+  SolverState st{};
+  st.stop2 = 1;
+  int enqueued = 0;
+  int restarts = 0;
+  for (;;) {
+    while (poll.pending < 2) {
+      const int n = next_chunk(st, enqueued, p->max_iter);
+      if (n <= 0) break;
+      for (int k = 0; k < n; ++k) {
+        const int i = enqueued + k;
+        // t = L p, alpha = rho / <p, t>; x += alpha p, r -= alpha t, beta; p = r + beta p
+        launch_lap_packed(g, w.U64, w.p, w.t, m2, G_ITER, F_ALPHA, w.st, w.partials, s, clock_at(clk, 0, i));
+        launch_lap_update(g, w.t, w.r, w.p, w.x, w.st, w.partials, s, clock_at(clk, 1, i));
+        launch_lap_p_update(g, w.r, w.p, w.st, s, clock_at(clk, 2, i));
+      }
+      enqueued += n;
+      HIP_TRY(hipGetLastError());
+      if ((rc = poll.post(w.st))) return rc;
+    }
+    if (poll.pending == 0) break;
+    if ((rc = poll.wait(&st))) return rc;
+    if (st.status != 0) {
+      if ((rc = poll.drain(&st))) return rc;
+      if (st.status != 1) break;
+      // verify with the residual recomputed from x
+      launch_lap_residual(g, w.U64, w.x, w.b, w.r, m2, G_FINAL, F_TRUE, w.st, w.partials, s);
+      if ((rc = poll.post(w.st))) return rc;
+      if ((rc = poll.drain(&st))) return rc;
+      if (st.rho_true <= st.stop2 || enqueued >= p->max_iter || restarts >= 5) break;
+      ++restarts;
+      launch_restart(w.st, s);
+      launch_lap_copy(g, w.r, w.p, G_ALWAYS, w.st, s);
+      HIP_TRY(hipGetLastError());
+      continue;
+    }
+  }
+  if ((rc = poll.drain(&st))) return rc;
+  const double iter_rel = std::sqrt(st.rho / (st.bnorm2 > 0 ? st.bnorm2 : 1.0));
+  if ((st.status != 1 || st.rho_true > st.stop2) && (st.status == 0 || st.status == 1)) {
+    // not converged within max_iter: report the true residual of the last iterate
+    launch_lap_residual(g, w.U64, w.x, w.b, w.r, m2, G_FINAL, F_TRUE, w.st, w.partials, s);
+    if ((rc = poll.post(w.st))) return rc;
+    if ((rc = poll.drain(&st))) return rc;
+  }
+  launch_lap_unpack(g, w.x, x, c64, s);
+  HIP_TRY(hipGetLastError());
+  if ((rc = copy_history(w.hist, p, s, st.iter))) return rc;
+  HIP_TRY(hipStreamSynchronize(s));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (res) clock_read(clk, enqueued, 3, res->kernel_seconds);
+  int code;
+  if (st.status < 0) code = status_to_code(st.status);
+  else if (st.rho_true <= st.stop2) code = WD_OK;
+  else code = fail(WD_NOT_CONVERGED, "not converged in %d iterations (true rel. residual %.3e)", st.iter,
+                   std::sqrt(st.rho_true / (st.bnorm2 > 0 ? st.bnorm2 : 1.0)));
+  return fill_result(res, st, code, secs, iter_rel);
+}
+
 }  // namespace
+
+extern "C" int laplace_apply(const wd_lattice* lat, double m2, const void* U, const void* psi, void* out,
+                             void* stream) {
+  int rc = check_lattice(lat);
+  if (rc) return rc;
+  if (!U || !psi || !out) return fail(WD_ERR_INVALID, "NULL field pointer");
+  if (psi == out) return fail(WD_ERR_INVALID, "in and out must not alias");
+  if (!std::isfinite(m2)) return fail(WD_ERR_INVALID, "m2 is not finite");
+  launch_lap_canonical(make_geom(lat->L, false), U, psi, out, m2, as_stream(stream));
+  HIP_TRY(hipGetLastError());
+  return WD_OK;
+}
+
+extern "C" size_t laplace_workspace_bytes(const wd_lattice* lat, const wd_cg_params* params) {
+  if (check_lattice(lat)) return 0;
+  if (validate_lap_params(params)) return 0;
+  return layout_lap(nullptr, packed_geom(lat), params->history_len).bytes;
+}
+
+extern "C" int laplace_cg_solve(const wd_lattice* lat, double m2, const void* U, const void* b, void* x,
+                                const wd_cg_params* params, wd_cg_result* result, void* workspace, size_t ws_bytes,
+                                void* stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (result) std::memset(result, 0, sizeof(*result));
+  int rc = check_lattice(lat);
+  if (rc) return rc;
+  if ((rc = validate_lap_params(params))) return rc;
+  if (!U || !b || !x) return fail(WD_ERR_INVALID, "NULL field pointer");
+  if (b == x) return fail(WD_ERR_INVALID, "b and x must not alias");
+  if (!std::isfinite(m2)) return fail(WD_ERR_INVALID, "m2 is not finite");
+  const Geom g = packed_geom(lat);
+  const size_t need = layout_lap(nullptr, g, params->history_len).bytes;
+  if (!workspace || ws_bytes < need)
+    return fail(WD_ERR_WORKSPACE, "workspace of %zu bytes given, %zu needed", workspace ? ws_bytes : 0, need);
+  return lap_cg(g, m2, U, b, x, params, result, workspace, as_stream(stream), t0);
+}
 
 extern "C" int cg_solve(const wd_lattice* lat, double mass, const void* U, const void* b, void* x,
                         const wd_cg_params* params, wd_cg_result* result, void* workspace, size_t ws_bytes,

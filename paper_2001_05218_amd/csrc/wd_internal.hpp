@@ -154,6 +154,8 @@ void launch_ring_reset(SolverState* st, hipStream_t s);
 void launch_set_ring(SolverState* st, double* alpha_hist, int flush_at, int ring_len, hipStream_t s);
 // x(FP64) += xhat; xhat = 0
 void launch_accumulate(const Geom& g, SpinorBuf x64, SpinorBuf xhat, int gate, SolverState* st, hipStream_t s);
+// Sum of the first n per-workgroup partials, then the state update fin (gated).
+void launch_finalize_n(int n, double* partials, SolverState* st, int fin, int gate, hipStream_t s);
 // ||v||^2 -> fin
 void launch_norm2(const Geom& g, SpinorBuf v, int gate, int fin, SolverState* st, double* partials, hipStream_t s);
 // Workspace of the batched persistent solver (wd_batched.hip).
@@ -161,6 +163,30 @@ size_t batched_workspace_bytes(const Geom& g, int nrhs, int hist_len);
 // Batched solve after argument validation; writes a message to err on failure.
 int batched_solve(const Geom& g, double mass, const void* U, int nrhs, const void* B, void* X,
                   const ::wd_cg_params* p, ::wd_cg_result* res, void* ws, hipStream_t s, char* err, size_t errlen);
+
+// ---- gauge-covariant Laplacian on colour vectors (wd_laplace.hip); packed
+// colour fields are FP64, 3 words per site; links are the FP64 packed gauge field.
+// out = L in on canonical (V, 3) complex128 fields
+void launch_lap_canonical(const Geom& g, const void* U, const void* in, void* out, double m2, hipStream_t s);
+// canonical (V, 3) colour field (complex128, or complex64 if c64) <-> packed FP64
+void launch_lap_pack(const Geom& g, const void* in, int c64, void* out, hipStream_t s);
+void launch_lap_unpack(const Geom& g, const void* in, void* out, int c64, hipStream_t s);
+// t = L p; Re <p, t> -> fin (F_ALPHA in the solver, F_NONE for a plain application)
+void launch_lap_packed(const Geom& g, const void* U, const void* p, void* t, double m2, int gate, int fin,
+                       SolverState* st, double* partials, hipStream_t s, const EventPair* ev = nullptr);
+// r = b - L x; ||r||^2 -> fin
+void launch_lap_residual(const Geom& g, const void* U, const void* x, const void* b, void* r, double m2, int gate,
+                         int fin, SolverState* st, double* partials, hipStream_t s);
+// x += alpha p; r -= alpha t; ||r||^2 -> F_BETA (gate G_ITER)
+void launch_lap_update(const Geom& g, const void* t, void* r, const void* p, void* x, SolverState* st,
+                       double* partials, hipStream_t s, const EventPair* ev = nullptr);
+// p = r + beta p (gate G_ITER)
+void launch_lap_p_update(const Geom& g, const void* r, void* p, SolverState* st, hipStream_t s,
+                         const EventPair* ev = nullptr);
+// ||v||^2 -> fin
+void launch_lap_norm2(const Geom& g, const void* v, int fin, SolverState* st, double* partials, hipStream_t s);
+// dst = src, or dst = 0 when src is null (gated)
+void launch_lap_copy(const Geom& g, const void* src, void* dst, int gate, SolverState* st, hipStream_t s);
 
 // G(a, b) force on canonical complex128 spinors -> canonical complex128 links.
 void launch_force(const Geom& g, const void* a, const void* b, double coeff, int accumulate, void* F, hipStream_t s);

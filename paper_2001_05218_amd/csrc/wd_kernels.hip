@@ -6,30 +6,12 @@
 
 #include "wd_dslash.hpp"
 #include "wd_internal.hpp"
+#include "wd_reduce.hpp"
 #include "wd_tiled.hpp"
 
 namespace wd {
 
 // ------------------------------------------------------------ reductions
-
-// Sum over a 256-thread workgroup in a fixed order: butterfly within each
-// 64-lane wavefront, then the four wavefront sums in index order.
-__device__ __forceinline__ double block_sum(double v) {
-  __shared__ double wsum[kBlock / 64];
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  const int lane = threadIdx.x & 63;
-  const int wid = threadIdx.x >> 6;
-  if (lane == 0) wsum[wid] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int i = 0; i < kBlock / 64; ++i) t += wsum[i];
-  }
-  __syncthreads();
-  return t;   // valid in thread 0
-}
 
 __device__ __forceinline__ bool finite_d(double x) { return x - x == 0.0; }
 
@@ -112,28 +94,7 @@ __device__ void finalize(SolverState* st, int fin, double sum) {
   }
 }
 
-// Per-workgroup partial of a grid-wide sum, written with a plain store; the
-// launcher follows the kernel with k_finalize, which adds the partials in
-// index order (deterministic) and applies `fin` to the solver state. Keeping
-// the cross-workgroup step in its own launch avoids device-scope
-// acquire/release per workgroup, which on a multi-XCD part writes back and
-// invalidates the XCD's L2 and would throw away the stencil's neighbour reuse.
-__device__ __forceinline__ void store_partial(double v, double* partials) {
-  const double bs = block_sum(v);
-  if (threadIdx.x == 0) partials[blockIdx.x] = bs;
-}
-
 constexpr int kFinBlock = 1024;
-
-__device__ __forceinline__ bool gate_open(const SolverState* st, int gate) {
-  if (gate == G_ALWAYS || gate == G_FINAL) return true;
-  const int status = st->status;
-  if (gate == G_ITER) return status == 0 && st->inner_done == 0;
-  if (gate == G_FLUSH) return status == 0 && st->flush_at > 0 && st->npend >= st->flush_at;
-  // G_RELIABLE
-  return status == 0 && (st->inner_done != 0 || st->iter - st->last_update >= st->interval ||
-                         st->rho <= st->delta2 * st->rho_update);
-}
 
 // Sum of n partials in a fixed order, then the state update `fin`. Runs with
 // the same gate as the kernel that wrote the partials (which did not change
@@ -170,8 +131,12 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(const double* __restrict
   }
 }
 
+void launch_finalize_n(int n, double* partials, SolverState* st, int fin, int gate, hipStream_t s) {
+  k_finalize<<<1, kFinBlock, 0, s>>>(partials, n, st, fin, gate);
+}
+
 static void launch_finalize(const Geom& g, double* partials, SolverState* st, int fin, int gate, hipStream_t s) {
-  k_finalize<<<1, kFinBlock, 0, s>>>(partials, g.nblocks, st, fin, gate);
+  launch_finalize_n(g.nblocks, partials, st, fin, gate, s);
 }
 
 // ------------------------------------------------------- spinor dispatch

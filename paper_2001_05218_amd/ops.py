@@ -185,6 +185,74 @@ def cg_solve_batched(U: torch.Tensor, B: torch.Tensor, mass: float, tol: float =
     return X, [r.as_dict() for r in res]
 
 
+# ---- the gauge-covariant Laplacian (colour vectors) ------------------------
+
+def colour_shape(dims):
+    lx, ly, lz, lt = dims
+    return (lt, lz, ly, lx, 3)
+
+
+def dims_of_colour(v: torch.Tensor):
+    if v.dim() != 5 or v.shape[-1] != 3:
+        raise ValueError(f"colour-field shape {tuple(v.shape)} is not (Lt, Lz, Ly, Lx, 3)")
+    lt, lz, ly, lx = v.shape[:4]
+    return (int(lx), int(ly), int(lz), int(lt))
+
+
+def laplace_apply(U: torch.Tensor, psi: torch.Tensor, m2: float, out: torch.Tensor | None = None) -> torch.Tensor:
+    """L psi on canonical complex128 colour fields (Lt, Lz, Ly, Lx, 3)."""
+    dims = dims_of_colour(psi)
+    _need(psi, "psi", (torch.complex128,), colour_shape(dims))
+    _need(U, "U", (torch.complex128,), gauge_shape(dims))
+    if out is None:
+        out = torch.empty_like(psi)
+    _need(out, "out", (torch.complex128,), psi.shape)
+    lib = _lib.load()
+    rc = lib.laplace_apply(ctypes.byref(_lib.lattice(dims)), float(m2), U.data_ptr(), psi.data_ptr(),
+                           out.data_ptr(), _stream(psi.device))
+    _lib.check(rc, "laplace_apply")
+    return out
+
+
+def laplace_workspace_bytes(dims, params) -> int:
+    lib = _lib.load()
+    n = lib.laplace_workspace_bytes(ctypes.byref(_lib.lattice(dims)), ctypes.byref(params))
+    if n == 0:
+        raise _lib.WilsonError(_lib.WD_ERR_INVALID, "laplace_workspace_bytes", _lib.last_error())
+    return int(n)
+
+
+def laplace_cg_solve(U: torch.Tensor, b: torch.Tensor, m2: float, tol: float = 1e-10, max_iter: int = 10000,
+                     x0: torch.Tensor | None = None, history: int = 0, workspace: torch.Tensor | None = None,
+                     raise_on_nonconvergence: bool = True, profile: bool = False):
+    """Solve L x = b (FP64 CG). b: complex128 or complex64 (Lt, Lz, Ly, Lx, 3).
+    Returns (x, info) like cg_solve."""
+    dims = dims_of_colour(b)
+    _need(b, "b", (torch.complex128, torch.complex64), colour_shape(dims))
+    _need(U, "U", (torch.complex128,), gauge_shape(dims))
+    io = WD_C64 if b.dtype == torch.complex64 else WD_C128
+    params, hist = make_params(tol, max_iter, "f64", 50, "source", io, x0 is None, history, profile)
+    if x0 is None:
+        x = torch.empty_like(b)
+    else:
+        _need(x0, "x0", (b.dtype,), b.shape)
+        x = x0.clone()
+    need = laplace_workspace_bytes(dims, params)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=b.device)
+    res = _lib.WdCgResult()
+    lib = _lib.load()
+    rc = lib.laplace_cg_solve(ctypes.byref(_lib.lattice(dims)), float(m2), U.data_ptr(), b.data_ptr(),
+                              x.data_ptr(), ctypes.byref(params), ctypes.byref(res), workspace.data_ptr(),
+                              workspace.numel(), _stream(b.device))
+    ok = (_lib.WD_OK,) if raise_on_nonconvergence else (_lib.WD_OK, _lib.WD_NOT_CONVERGED)
+    _lib.check(rc, "laplace_cg_solve", ok)
+    info = res.as_dict()
+    if hist is not None:
+        info["history"] = list(hist)[: min(history, res.iterations)]
+    return x, info
+
+
 # ---- packed fields -------------------------------------------------------
 
 def _gauge_dims(U):

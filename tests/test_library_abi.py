@@ -167,3 +167,27 @@ def test_workspace_grows_with_ring(lib):
     c = lib.wd_workspace_bytes(_lat(dims), ctypes.byref(_params(inner_prec=0, ring_len=8)), 1)
     d = lib.wd_workspace_bytes(_lat(dims), ctypes.byref(_params(inner_prec=0, ring_len=40)), 1)
     assert c == d
+
+
+def test_laplace_rejects_bad_args(lib):
+    lat = _lat((4, 4, 4, 4))
+    assert lib.laplace_apply(_lat((4, 1, 4, 4)), 0.1, 1, 2, 3, None) == _lib.WD_ERR_INVALID
+    assert lib.laplace_apply(lat, 0.1, None, 2, 3, None) == _lib.WD_ERR_INVALID
+    assert lib.laplace_apply(lat, 0.1, 1, 2, 2, None) == _lib.WD_ERR_INVALID
+    assert lib.laplace_apply(lat, float("inf"), 1, 2, 3, None) == _lib.WD_ERR_INVALID
+    p = _params()
+    need = lib.laplace_workspace_bytes(lat, ctypes.byref(p))
+    # state + partials + history + FP64 links (576 B/site) + 5 colour fields (48 B/site)
+    assert need >= 256 * (576 + 5 * 48)
+    res = _lib.WdCgResult()
+    rc = lib.laplace_cg_solve(lat, 0.1, 1, 2, 3, ctypes.byref(p), ctypes.byref(res), 4, need - 1, None)
+    assert rc == _lib.WD_ERR_WORKSPACE
+    assert lib.laplace_cg_solve(lat, 0.1, 1, 2, 2, ctypes.byref(p), None, 4, need, None) == _lib.WD_ERR_INVALID
+    assert lib.laplace_cg_solve(lat, float("nan"), 1, 2, 3, ctypes.byref(p), None, 4, need, None) == _lib.WD_ERR_INVALID
+    f32 = _params(inner_prec=1)
+    assert lib.laplace_workspace_bytes(lat, ctypes.byref(f32)) == 0
+    assert "inner_prec" in _lib.last_error()
+    assert lib.laplace_cg_solve(lat, 0.1, 1, 2, 3, ctypes.byref(f32), None, 4, need, None) == _lib.WD_ERR_INVALID
+    bad = _params(tol=0.0)
+    assert lib.laplace_cg_solve(lat, 0.1, 1, 2, 3, ctypes.byref(bad), None, 4, need, None) == _lib.WD_ERR_INVALID
+    assert "tol" in _lib.last_error()
