@@ -54,8 +54,9 @@ typedef struct {
 /* storage / arithmetic precision of the solver's inner iterations.
  * WD_F16 spinors carry one FP32 magnitude per site (values stored divided by it).
  * WD_I8 is fixed point: spinors as 24 signed bytes per site, q = round(127 v / m)
- * with m the site's largest |component| (kept as FP32 per site); links as int16
- * q = round(16384 u), so entries must lie within +-2 (larger ones saturate). */
+ * with m the site's largest |component| (kept as FP32 per site); links as FP16,
+ * as for WD_F16 (the stencil then runs its products in half precision with
+ * FP32 sums, exact for these inputs). */
 enum { WD_F64 = 0, WD_F32 = 1, WD_BF16 = 2, WD_F16 = 3, WD_I8 = 4 };
 /* OR-ed into the precision of a packed GAUGE field (wd_gauge_bytes, wd_pack_gauge,
  * wilson_apply_packed): store rows 0 and 1 of each link only and rebuild row 2

@@ -13,8 +13,10 @@
 //   spinor FP32 :  6 words x 16 B (two complex<float>)
 //   spinor BF16 :  3 words x 16 B (four complex<bf16>)
 //   spinor FP16 :  3 words x 16 B (four complex<fp16>) + one FP32 scale per site
+//   spinor int8 :  3 words x  8 B (four complex<int8>) + one FP32 scale per site
 //   links        : per site 4 directions x 9 words, one complex entry per
-//                  word (16 B FP64, 8 B FP32, 4 B BF16/FP16), row-major colour
+//                  word (16 B FP64, 8 B FP32, 4 B BF16/FP16; the int8
+//                  storage keeps FP16 links), row-major colour
 // The padded volume Vpad rounds V up to a multiple of 256 sites (one
 // workgroup); padding sites are never read as neighbours and never written.
 #pragma once
@@ -221,17 +223,16 @@ __device__ __forceinline__ float h_bits2f(uint32_t b) {
   return (float)__builtin_bit_cast(_Float16, (uint16_t)(b & 0xffffu));
 }
 
-// Fixed-point links of the int8 storage: each real as an int16 q, value
-// q / kLinkFix (range +-2, resolution 6.1e-5); a pair (re low, im high) per word.
-constexpr float kLinkFix = 16384.0f;
-__device__ __forceinline__ int fix16(float v) {
-  return (int)rintf(fminf(fmaxf(v * kLinkFix, -32767.0f), 32767.0f));
+// int8 values -> half2 words, exact (|q| <= 127 is an integer of FP16's range):
+// flipping the sign bit makes each byte q + 128, and the half with high byte
+// 0x64 and low byte q + 128 is 1024 + q + 128; one subtraction of 1152 leaves q.
+// Returns the half2 (re, im) of the complex number in bytes 2j, 2j + 1 of d.
+__device__ __forceinline__ uint32_t i8x2_to_h2(uint32_t d, int j) {
+  const uint32_t x = d ^ 0x80808080u;
+  const uint32_t biased = __builtin_amdgcn_perm(0x64646464u, x, j ? 0x04030402u : 0x04010400u);
+  const wd_f16x2 bias = {(_Float16)1152.0f, (_Float16)1152.0f};
+  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(wd_f16x2, biased) - bias);
 }
-__device__ __forceinline__ uint32_t pack_i16x2(float lo, float hi) {
-  return ((uint32_t)fix16(lo) & 0xffffu) | ((uint32_t)fix16(hi) << 16);
-}
-__device__ __forceinline__ float i16_raw2f(uint32_t b) { return (float)(int)(int16_t)(uint16_t)(b & 0xffffu); }
-__device__ __forceinline__ float i16_bits2f(uint32_t b) { return i16_raw2f(b) * (1.0f / kLinkFix); }
 
 __device__ __forceinline__ size_t word_index(int s, int nwords, int w) {
   return ((size_t)(s >> 6) * nwords + w) * kSiteBlock + (s & 63);
@@ -529,10 +530,7 @@ template <int P> __device__ __forceinline__ void unpack_link16(uint32_t d, float
   if constexpr (P == P_BF16) {
     re = bf_bits2f(d & 0xffffu);
     im = bf_bits2f(d >> 16);
-  } else if constexpr (P == P_I8) {
-    re = i16_bits2f(d);
-    im = i16_bits2f(d >> 16);
-  } else {
+  } else {   // FP16 pairs (also the links of the int8 storage)
     re = h_bits2f(d);
     im = h_bits2f(d >> 16);
   }
@@ -566,19 +564,7 @@ template <> struct PackedGauge<P_F16> {
   }
 };
 
-template <> struct PackedGauge<P_I8> {   // int16 fixed-point links
-  using Real = float;
-  WD_GAUGE_FORWARDERS
-  const uint32_t* data;
-  __device__ __forceinline__ void load(int s, int mu, Real u[18]) const {
-#pragma unroll
-    for (int e = 0; e < 9; ++e) {
-      uint32_t d = data[word_index(s, 36, mu * 9 + e)];
-      u[2 * e] = i16_bits2f(d);
-      u[2 * e + 1] = i16_bits2f(d >> 16);
-    }
-  }
-};
+template <> struct PackedGauge<P_I8> : PackedGauge<P_F16> {};   // int8 storage keeps FP16 links
 
 // Canonical boundary layout: (4, Lt, Lz, Ly, Lx, 3, 3) complex128.
 struct CanonGauge {

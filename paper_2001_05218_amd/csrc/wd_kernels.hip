@@ -169,9 +169,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_gauge(Geom g, const double2* __
       else if constexpr (P == P_F32) reinterpret_cast<float2*>(out)[w] = make_float2((float)d.x, (float)d.y);
       else if constexpr (P == P_BF16)
         reinterpret_cast<uint32_t*>(out)[w] = pack_bf16x2((float)d.x, (float)d.y);
-      else if constexpr (P == P_I8)
-        reinterpret_cast<uint32_t*>(out)[w] = pack_i16x2((float)d.x, (float)d.y);
-      else
+      else   // FP16, and the FP16 links of the int8 storage
         reinterpret_cast<uint32_t*>(out)[w] = pack_f16x2((float)d.x, (float)d.y);
     }
   }
@@ -188,7 +186,6 @@ __global__ __launch_bounds__(kBlock) void k_pack_gauge_rows2(Geom g, const doubl
     for (int e = 0; e < 6; ++e) {
       const double2 d = src[e];
       out[word_index(s, 24, mu * 6 + e)] = (P == P_BF16) ? pack_bf16x2((float)d.x, (float)d.y)
-                                           : (P == P_I8) ? pack_i16x2((float)d.x, (float)d.y)
                                                          : pack_f16x2((float)d.x, (float)d.y);
     }
   }
@@ -410,10 +407,23 @@ __global__ __launch_bounds__(kBlock) WD_TILED_OCCUPANCY void k_cg_update_tiled(G
   float sc;
   PackedSpinor<P>::pack(rv, d, sc);
   rs.store_raw(s, d, sc);
-  PackedSpinor<P>::unpack(d, sc, rv);   // the norm of what the next iteration reads
+  // the norm of what the next iteration reads
   double n2 = 0.0;
+  if constexpr (P == P_I8) {
+    // factor^2 times the sum of the squared bytes, exact in int32 (<= 24 * 127^2)
+    int q2 = 0;
 #pragma unroll
-  for (int i = 0; i < 24; ++i) n2 += (double)rv[i] * (double)rv[i];
+    for (int w = 0; w < 3; ++w) {
+      q2 = __builtin_amdgcn_sdot4((int)d[w].x, (int)d[w].x, q2, false);
+      q2 = __builtin_amdgcn_sdot4((int)d[w].y, (int)d[w].y, q2, false);
+    }
+    const double f = (double)PackedSpinor<P>::raw_factor(sc);
+    n2 = f * f * (double)q2;
+  } else {
+    PackedSpinor<P>::unpack(d, sc, rv);
+#pragma unroll
+    for (int i = 0; i < 24; ++i) n2 += (double)rv[i] * (double)rv[i];
+  }
   store_partial(n2, partials);
 }
 

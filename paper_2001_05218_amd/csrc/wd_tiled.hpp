@@ -43,6 +43,31 @@ struct TileLds {
   float scale[kTileSlots];
 };
 
+// int8 storage: staged already converted, 12 half2 words (one complex each,
+// index spin * 3 + colour) per slot, and the slot's value factor scale / 127.
+template <>
+struct TileLds<P_I8> {
+  uint4 h[3][kTileSlots];
+  float f[kTileSlots];
+};
+
+// Store one site's spinor words (and scale) into an LDS slot.
+template <int P>
+__device__ __forceinline__ void stage_slot(TileLds<P>& lds, int slot, const typename SpinorWord<P>::T* src,
+                                           const float* scale, int s) {
+#pragma unroll
+  for (int w = 0; w < 3; ++w) lds.w[w][slot] = src[word_index(s, 3, w)];
+  if constexpr (kScaled<P>) lds.scale[slot] = scale[s];
+}
+__device__ __forceinline__ void stage_slot(TileLds<P_I8>& lds, int slot, const uint2* src, const float* scale, int s) {
+#pragma unroll
+  for (int w = 0; w < 3; ++w) {
+    const uint2 d = src[word_index(s, 3, w)];
+    lds.h[w][slot] = make_uint4(i8x2_to_h2(d.x, 0), i8x2_to_h2(d.x, 1), i8x2_to_h2(d.y, 0), i8x2_to_h2(d.y, 1));
+  }
+  lds.f[slot] = scale[s] * (1.0f / 127.0f);
+}
+
 // Links are stored either as all 9 entries (18 reals) or, for SU(3) fields,
 // as rows 0 and 1 only (12 reals; row 2 = conj(row0 x row1) is rebuilt on use).
 template <bool C12> struct LinkFormat {
@@ -69,9 +94,7 @@ __device__ __forceinline__ void tile_stage(const Geom& g, int T, const void* Uv,
   for (int mu = 0; mu < 4; ++mu)
 #pragma unroll
     for (int e = 0; e < NE; ++e) lk[4 + mu][e] = U[word_index(nb.bwd[mu], NW, mu * NE + e)];
-#pragma unroll
-  for (int w = 0; w < 3; ++w) lds.w[w][l] = src[word_index(s, 3, w)];
-  if constexpr (kScaled<P>) lds.scale[l] = in.scale[s];
+  stage_slot(lds, l, src, in.scale, s);
   // halo: wavefront mu stages the two mu faces
   const int mu = l >> 6;
   const int f = l & 63;
@@ -81,15 +104,8 @@ __device__ __forceinline__ void tile_stage(const Geom& g, int T, const void* Uv,
   const int sm = tile_step(g, T, b, mu, -1) * kTileSites + face_insert(f, mu, 3);
   const int slot_p = kTileSites + (2 * mu) * 64 + f;
   const int slot_m = kTileSites + (2 * mu + 1) * 64 + f;
-#pragma unroll
-  for (int w = 0; w < 3; ++w) {
-    lds.w[w][slot_p] = src[word_index(sp, 3, w)];
-    lds.w[w][slot_m] = src[word_index(sm, 3, w)];
-  }
-  if constexpr (kScaled<P>) {
-    lds.scale[slot_p] = in.scale[sp];
-    lds.scale[slot_m] = in.scale[sm];
-  }
+  stage_slot(lds, slot_p, src, in.scale, sp);
+  stage_slot(lds, slot_m, src, in.scale, sm);
 }
 
 // ---- FP64 / FP32 stencils on the tiled order. A workgroup owns one 4^4
@@ -167,16 +183,9 @@ __device__ __forceinline__ float tile_spinor_raw(const TileLds<P>& lds, int slot
   return PackedSpinor<P>::raw_factor(kScaled<P> ? lds.scale[slot] : 1.0f);
 }
 
-// Links as link_from returns them are the true links divided by kLinkUnit<P>
-// (int16 fixed point is left unscaled until the hop factor).
-template <int P> constexpr float kLinkUnit = (P == P_I8) ? 1.0f / kLinkFix : 1.0f;
-
 // Unpack a prefetched link at its point of use. The empty asm makes each raw
 // word opaque here, so the compiler cannot unpack all eight links right after
 // their loads (which would keep 144 floats live instead of 72 raw words).
-// For int16 fixed point the entries come back in units of 1 / kLinkFix (the
-// hop multiplies by kLinkUnit<P> once); the rebuilt row 2 is brought to the
-// same units.
 template <int P, bool C12>
 __device__ __forceinline__ void link_from(const uint32_t raw[9], float u[18]) {
   constexpr int NE = LinkFormat<C12>::entries;
@@ -184,20 +193,9 @@ __device__ __forceinline__ void link_from(const uint32_t raw[9], float u[18]) {
   for (int e = 0; e < NE; ++e) {
     uint32_t r = raw[e];
     asm volatile("" : "+v"(r));
-    if constexpr (P == P_I8) {
-      u[2 * e] = i16_raw2f(r);
-      u[2 * e + 1] = i16_raw2f(r >> 16);
-    } else {
-      unpack_link16<P>(r, u[2 * e], u[2 * e + 1]);
-    }
+    unpack_link16<P>(r, u[2 * e], u[2 * e + 1]);
   }
-  if constexpr (C12) {
-    su3_third_row(u);
-    if constexpr (P == P_I8) {
-#pragma unroll
-      for (int i = 12; i < 18; ++i) u[i] *= 1.0f / kLinkFix;
-    }
-  }
+  if constexpr (C12) su3_third_row(u);
 }
 
 template <int P, bool C12, int MU, bool DAG>
@@ -210,18 +208,151 @@ __device__ __forceinline__ void tile_hop(const TileLds<P>& lds, const uint32_t l
   const int slot_f = (lm < 3) ? l + ls : kTileSites + (2 * MU) * 64 + fp;
   const int slot_b = (lm > 0) ? l - ls : kTileSites + (2 * MU + 1) * 64 + fp;
   float psi[24], h[12], w[12], u[18];
-  float f = tile_spinor_raw<P>(lds, slot_f, psi) * kLinkUnit<P>;
+  float f = tile_spinor_raw<P>(lds, slot_f, psi);
   link_from<P, C12>(lk[MU], u);
   project<MU, SF>(psi, h);
   su3_mul_half<false>(u, h, w);
   reconstruct_fma<MU, SF>(acc, w, f);
-  f = tile_spinor_raw<P>(lds, slot_b, psi) * kLinkUnit<P>;
+  f = tile_spinor_raw<P>(lds, slot_b, psi);
   link_from<P, C12>(lk[4 + MU], u);
   project<MU, SB>(psi, h);
   su3_mul_half<true>(u, h, w);
   reconstruct_fma<MU, SB>(acc, w, f);
   // keep the scheduler from hoisting the next hop's LDS reads and unpacking
   // above this one (that multiplies the live registers for 16-bit data)
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// ---- int8 storage: hops in packed half precision with FP32 dot products.
+// gfx950's v_dot2_f32_f16 multiplies the two halves of two half2 words and
+// adds both products to an FP32 accumulator, so a complex multiply-add takes
+// two instructions instead of four FP32 FMAs, and a spin projection of two
+// half2 complex numbers is one v_pk_add_f16. Nothing is lost to the format:
+// the staged int8 values are exact in half, so are their projections
+// (|q1 +- q2| <= 254), the products of two halves are exact in FP32, and the
+// links are FP16 already; only the FP32 sums round, as in the FP32 path.
+
+// a.x * b.x + a.y * b.y + c, FP32 sum of exact products.
+__device__ __forceinline__ float dot2(uint32_t a, uint32_t b, float c) {
+  return __builtin_amdgcn_fdot2(__builtin_bit_cast(wd_f16x2, a), __builtin_bit_cast(wd_f16x2, b), c, false);
+}
+
+// Written out: given the same sum as half2 vector code, the compiler builds
+// the swapped or negated first operand with separate instructions (2-3 per
+// form instead of none). v_pk_add_f16 is a plain VALU op: no wait states.
+#define WD_PK_ADD_F16(r, a, b, MODS) asm("v_pk_add_f16 %0, %1, %2 " MODS : "=v"(r) : "v"(a), "v"(b))
+
+// One form of h = a + i^N b (a, b, h complex as half2 (re, im)), in one
+// v_pk_add_f16 whose source selects and negations build the form:
+//   F = 0: (h.re, h.im)   F = 1: (h.re, -h.im)   F = 2: (h.im, h.re)   F = 3: (h.im, -h.re)
+// U h needs forms 1 and 2 (re = sum dot2(u, form 1), im = sum dot2(u, form 2));
+// U^+ h needs forms 0 and 3.
+template <int N, int F>
+__device__ __forceinline__ uint32_t proj_form(uint32_t a, uint32_t b) {
+  uint32_t r;
+  if constexpr (N == 0 && F == 0) WD_PK_ADD_F16(r, a, b, "op_sel:[0,0] op_sel_hi:[1,1] neg_lo:[0,0] neg_hi:[0,0]");
+  if constexpr (N == 0 && F == 1) WD_PK_ADD_F16(r, a, b, "op_sel:[0,0] op_sel_hi:[1,1] neg_lo:[0,0] neg_hi:[1,1]");
+  if constexpr (N == 0 && F == 2) WD_PK_ADD_F16(r, a, b, "op_sel:[1,1] op_sel_hi:[0,0] neg_lo:[0,0] neg_hi:[0,0]");
+  if constexpr (N == 0 && F == 3) WD_PK_ADD_F16(r, a, b, "op_sel:[1,1] op_sel_hi:[0,0] neg_lo:[0,0] neg_hi:[1,1]");
+  if constexpr (N == 1 && F == 0) WD_PK_ADD_F16(r, a, b, "op_sel:[0,1] op_sel_hi:[1,0] neg_lo:[0,1] neg_hi:[0,0]");
+  if constexpr (N == 1 && F == 1) WD_PK_ADD_F16(r, a, b, "op_sel:[0,1] op_sel_hi:[1,0] neg_lo:[0,1] neg_hi:[1,1]");
+  if constexpr (N == 1 && F == 2) WD_PK_ADD_F16(r, a, b, "op_sel:[1,0] op_sel_hi:[0,1] neg_lo:[0,0] neg_hi:[0,1]");
+  if constexpr (N == 1 && F == 3) WD_PK_ADD_F16(r, a, b, "op_sel:[1,0] op_sel_hi:[0,1] neg_lo:[0,0] neg_hi:[1,0]");
+  if constexpr (N == 2 && F == 0) WD_PK_ADD_F16(r, a, b, "op_sel:[0,0] op_sel_hi:[1,1] neg_lo:[0,1] neg_hi:[0,1]");
+  if constexpr (N == 2 && F == 1) WD_PK_ADD_F16(r, a, b, "op_sel:[0,0] op_sel_hi:[1,1] neg_lo:[0,1] neg_hi:[1,0]");
+  if constexpr (N == 2 && F == 2) WD_PK_ADD_F16(r, a, b, "op_sel:[1,1] op_sel_hi:[0,0] neg_lo:[0,1] neg_hi:[0,1]");
+  if constexpr (N == 2 && F == 3) WD_PK_ADD_F16(r, a, b, "op_sel:[1,1] op_sel_hi:[0,0] neg_lo:[0,1] neg_hi:[1,0]");
+  if constexpr (N == 3 && F == 0) WD_PK_ADD_F16(r, a, b, "op_sel:[0,1] op_sel_hi:[1,0] neg_lo:[0,0] neg_hi:[0,1]");
+  if constexpr (N == 3 && F == 1) WD_PK_ADD_F16(r, a, b, "op_sel:[0,1] op_sel_hi:[1,0] neg_lo:[0,0] neg_hi:[1,0]");
+  if constexpr (N == 3 && F == 2) WD_PK_ADD_F16(r, a, b, "op_sel:[1,0] op_sel_hi:[0,1] neg_lo:[0,1] neg_hi:[0,0]");
+  if constexpr (N == 3 && F == 3) WD_PK_ADD_F16(r, a, b, "op_sel:[1,0] op_sel_hi:[0,1] neg_lo:[0,1] neg_hi:[1,1]");
+  return r;
+}
+
+__device__ __forceinline__ uint32_t conj_h2(uint32_t u) { return u ^ 0x80000000u; }
+__device__ __forceinline__ uint32_t swap_h2(uint32_t u) { return (u >> 16) | (u << 16); }
+
+// Row 2 of an SU(3) link from FP16 rows 0 and 1 (words u[0..5]):
+// u2_k = conj(u0_i u1_j - u0_j u1_i), (i, j, k) cyclic, summed in FP32.
+__device__ __forceinline__ void su3_third_row_h(uint32_t u[9]) {
+  uint32_t c1[3], s1[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    c1[j] = conj_h2(u[3 + j]);
+    s1[j] = swap_h2(u[3 + j]);
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int i = (k + 1) % 3, j = (k + 2) % 3;
+    const float re = dot2(u[i], c1[j], -dot2(u[j], c1[i], 0.f));   // Re(u0_i u1_j - u0_j u1_i)
+    const float im = dot2(u[j], s1[i], -dot2(u[i], s1[j], 0.f));   // -Im(u0_i u1_j - u0_j u1_i)
+    u[6 + k] = pack_f16x2(re, im);
+  }
+}
+
+// acc += f * reconstruction of (U h) or (U^+ h), h the spin projection of the
+// staged neighbour in `slot`, f its value factor.
+template <int MU, int S, bool ADJ, bool C12>
+__device__ __forceinline__ void hop_h(const TileLds<P_I8>& lds, int slot, const uint32_t raw[9], float acc[24]) {
+  using T = SpinTab<MU>;
+  constexpr int sh = (S > 0) ? 0 : 2;
+  constexpr int N0 = (T::n0 + sh) & 3, N1 = (T::n1 + sh) & 3;
+  constexpr int FA = ADJ ? 0 : 1, FB = ADJ ? 3 : 2;
+  uint32_t psi[12];
+#pragma unroll
+  for (int w = 0; w < 3; ++w) {
+    const uint4 d = lds.h[w][slot];
+    psi[4 * w] = d.x;
+    psi[4 * w + 1] = d.y;
+    psi[4 * w + 2] = d.z;
+    psi[4 * w + 3] = d.w;
+  }
+  const float f = lds.f[slot];
+  uint32_t ha[6], hb[6];   // forms of the projection, index spin row * 3 + colour
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    ha[c] = proj_form<N0, FA>(psi[c], psi[(2 + T::p0) * 3 + c]);
+    hb[c] = proj_form<N0, FB>(psi[c], psi[(2 + T::p0) * 3 + c]);
+    ha[3 + c] = proj_form<N1, FA>(psi[3 + c], psi[(2 + T::p1) * 3 + c]);
+    hb[3 + c] = proj_form<N1, FB>(psi[3 + c], psi[(2 + T::p1) * 3 + c]);
+  }
+  constexpr int NE = LinkFormat<C12>::entries;
+  uint32_t u[9];
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    u[e] = raw[e];
+    asm volatile("" : "+v"(u[e]));   // keep the link words opaque until their hop
+  }
+  if constexpr (C12) su3_third_row_h(u);
+  float w[12];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      float re = 0.f, im = 0.f;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const int e = ADJ ? (j * 3 + i) : (i * 3 + j);
+        re = dot2(u[e], ha[k * 3 + j], re);
+        im = dot2(u[e], hb[k * 3 + j], im);
+      }
+      w[(k * 3 + i) * 2] = re;
+      w[(k * 3 + i) * 2 + 1] = im;
+    }
+  }
+  reconstruct_fma<MU, S>(acc, w, f);
+}
+
+template <bool C12, int MU, bool DAG>
+__device__ __forceinline__ void tile_hop_h(const TileLds<P_I8>& lds, const uint32_t lk[8][9], int l, float acc[24]) {
+  constexpr int SF = DAG ? +1 : -1;
+  constexpr int ls = 1 << (2 * MU);
+  const int lm = (l >> (2 * MU)) & 3;
+  const int fp = face_pos(l, MU);
+  const int slot_f = (lm < 3) ? l + ls : kTileSites + (2 * MU) * 64 + fp;
+  const int slot_b = (lm > 0) ? l - ls : kTileSites + (2 * MU + 1) * 64 + fp;
+  hop_h<MU, SF, false, C12>(lds, slot_f, lk[MU], acc);
+  hop_h<MU, -SF, true, C12>(lds, slot_b, lk[4 + MU], acc);
   __builtin_amdgcn_sched_barrier(0);
 }
 
@@ -233,12 +364,31 @@ __device__ __forceinline__ void tile_wilson(const TileLds<P>& lds, const uint32_
   float acc[24];
 #pragma unroll
   for (int i = 0; i < 24; ++i) acc[i] = 0.f;
-  tile_hop<P, C12, 0, DAG>(lds, lk, l, acc);
-  tile_hop<P, C12, 1, DAG>(lds, lk, l, acc);
-  tile_hop<P, C12, 2, DAG>(lds, lk, l, acc);
-  tile_hop<P, C12, 3, DAG>(lds, lk, l, acc);
   float c[24];
-  const float dc = diag * tile_spinor_raw<P>(lds, l, c);
+  float dc;
+  if constexpr (P == P_I8) {
+    tile_hop_h<C12, 0, DAG>(lds, lk, l, acc);
+    tile_hop_h<C12, 1, DAG>(lds, lk, l, acc);
+    tile_hop_h<C12, 2, DAG>(lds, lk, l, acc);
+    tile_hop_h<C12, 3, DAG>(lds, lk, l, acc);
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+      const uint4 d = lds.h[w][l];
+      const uint32_t q[4] = {d.x, d.y, d.z, d.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        c[8 * w + 2 * k] = h_bits2f(q[k]);
+        c[8 * w + 2 * k + 1] = h_bits2f(q[k] >> 16);
+      }
+    }
+    dc = diag * lds.f[l];
+  } else {
+    tile_hop<P, C12, 0, DAG>(lds, lk, l, acc);
+    tile_hop<P, C12, 1, DAG>(lds, lk, l, acc);
+    tile_hop<P, C12, 2, DAG>(lds, lk, l, acc);
+    tile_hop<P, C12, 3, DAG>(lds, lk, l, acc);
+    dc = diag * tile_spinor_raw<P>(lds, l, c);
+  }
 #pragma unroll
   for (int i = 0; i < 24; ++i) out[i] = fmaf(dc, c[i], -0.5f * acc[i]);
 }

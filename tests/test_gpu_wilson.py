@@ -67,10 +67,12 @@ def test_wilson_apply_packed_low_precision(dims, prec, bound):
     Ut, pt = to_dev(U), to_dev(psi)
     Up = wd.pack_gauge(Ut, prec)
     pin = wd.pack_spinor(pt, prec)
-    pout = wd.empty_packed_spinor(dims, prec, pt.device)
-    wd.wilson_apply_packed(Up, pin, pout, dims, 0.1, prec, False)
-    out = to_np(wd.unpack_spinor(pout, dims, prec))
-    assert rel(out, oracle.wilson_D(U, psi, 0.1)) <= bound
+    for dagger in (False, True):
+        pout = wd.empty_packed_spinor(dims, prec, pt.device)
+        wd.wilson_apply_packed(Up, pin, pout, dims, 0.1, prec, dagger)
+        out = to_np(wd.unpack_spinor(pout, dims, prec))
+        ref = (oracle.wilson_Ddag if dagger else oracle.wilson_D)(U, psi, 0.1)
+        assert rel(out, ref) <= bound
 
 
 def test_int8_storage_exact_on_its_grid():
