@@ -121,7 +121,9 @@ def parse():
     ap.add_argument("--dims", default=",".join(str(d) for d in DIMS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-other-rows", action="store_true",
-                    help="skip the batched, force and autograd measurements")
+                    help="skip the force, batched, autograd and Laplacian measurements")
+    ap.add_argument("--other-rows", default="force,batched,autograd,laplace",
+                    help="comma-separated subset of the other rows to measure")
     ap.add_argument("--cpu-sample-only", action="store_true", help=argparse.SUPPRESS)
     return ap.parse_args()
 
@@ -438,8 +440,16 @@ def main():
 
     other = None
     if not args.no_other_rows:
-        other = {"force_32x32x32x64": bench_force(dev, bt, x64), "batched_cg": bench_batched(dev),
-                 "autograd_solve": bench_autograd(dev), "laplace_cg_32x32x32x64": bench_laplace(dev, Ut)}
+        rows = set(args.other_rows.split(","))
+        other = {}
+        if "force" in rows:
+            other["force_32x32x32x64"] = bench_force(dev, bt, x64)
+        if "batched" in rows:
+            other["batched_cg"] = bench_batched(dev)
+        if "autograd" in rows:
+            other["autograd_solve"] = bench_autograd(dev)
+        if "laplace" in rows:
+            other["laplace_cg_32x32x32x64"] = bench_laplace(dev, Ut)
         log(f"other rows: {other}")
 
     cpu = None

@@ -91,6 +91,17 @@ __device__ __forceinline__ void sub_mul_dag(const double u[18], const CVec& v, C
   }
 }
 
+// h = U^+ v
+__device__ __forceinline__ CVec mul_dag(const double u[18], const CVec& v) {
+  CVec h;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) h.v[i] = 0.0;
+  sub_mul_dag(u, v, h);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) h.v[i] = -h.v[i];
+  return h;
+}
+
 // (L in)(s); also returns in(s) in `c` (the caller may need it for <p, L p>).
 template <class Gauge, class Vec>
 __device__ __forceinline__ CVec lap_site(const Geom& g, const Gauge& U, const Vec& in, int s, double diag, CVec& c) {
@@ -106,6 +117,71 @@ __device__ __forceinline__ CVec lap_site(const Geom& g, const Gauge& U, const Ve
     sub_mul(u, in.load(nb.fwd[mu]), acc);
     U.load(nb.bwd[mu], mu, u);
     sub_mul_dag(u, in.load(nb.bwd[mu]), acc);
+  }
+  return acc;
+}
+
+// Tiled order: one workgroup per 4^4 tile. The tile's input vectors are
+// staged in LDS, and each link is read once: U_mu(x) is loaded by the thread
+// at x, which applies it forward for x and, as U_mu(x)^+ in(x), hands the
+// backward term of the site x + mu over through LDS. Only at the tile's
+// lower faces does a thread load U_mu(x - mu) itself, and only at the faces
+// does it read a neighbour's vector from memory.
+struct LapTileLds {
+  double2 in[3][kBlock];
+  double2 up[3][kBlock];   // backward terms for the site above, current direction
+};
+
+__device__ __forceinline__ CVec lap_tile(const Geom& g, const PackedGauge<P_F64>& U, const PackedVec& in, int T,
+                                         double diag, CVec& c, LapTileLds& lds) {
+  const int l = threadIdx.x;
+  const int s = T * kBlock + l;
+  c = in.load(s);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) lds.in[k][l] = make_double2(c.v[2 * k], c.v[2 * k + 1]);
+  CVec acc;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) acc.v[i] = diag * c.v[i];
+  int b[4];
+  tile_coords(g, (uint32_t)T, b);
+  __syncthreads();
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    const int ls = 1 << (2 * mu);
+    const int lm = (l >> (2 * mu)) & 3;
+    double u[18];
+    U.load(s, mu, u);
+    CVec f;
+    if (lm < 3) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double2 d = lds.in[k][l + ls];
+        f.v[2 * k] = d.x;
+        f.v[2 * k + 1] = d.y;
+      }
+    } else {
+      f = in.load((tile_step(g, T, b, mu, +1) << 8) + (l - 3 * ls));
+    }
+    sub_mul(u, f, acc);
+    if (lm < 3) {
+      const CVec h = mul_dag(u, c);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) lds.up[k][l + ls] = make_double2(h.v[2 * k], h.v[2 * k + 1]);
+    }
+    __syncthreads();
+    if (lm > 0) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double2 d = lds.up[k][l];
+        acc.v[2 * k] -= d.x;
+        acc.v[2 * k + 1] -= d.y;
+      }
+    } else {
+      const int sb = (tile_step(g, T, b, mu, -1) << 8) + (l + 3 * ls);
+      U.load(sb, mu, u);
+      sub_mul_dag(u, in.load(sb), acc);
+    }
+    __syncthreads();   // lds.up is rewritten for the next direction
   }
   return acc;
 }
@@ -173,6 +249,7 @@ __global__ __launch_bounds__(kBlock) void k_lap_unpack(Geom g, const double2* in
 }
 
 // t = L p on packed fields; with fin != F_NONE, Re <p, t> per workgroup.
+template <bool TILE>
 __global__ __launch_bounds__(kBlock) void k_lap_packed(Geom g, const void* U, const double2* p, double2* t,
                                                        double diag, int gate, int fin, SolverState* st,
                                                        double* partials) {
@@ -180,9 +257,16 @@ __global__ __launch_bounds__(kBlock) void k_lap_packed(Geom g, const void* U, co
   const int T = xcd_tile(blockIdx.x, gridDim.x);
   const int s = T * kBlock + threadIdx.x;
   double d = 0.0;
-  if (s < g.V) {
+  const PackedVec in{const_cast<double2*>(p)};
+  if constexpr (TILE) {
+    __shared__ LapTileLds lds;
     CVec c;
-    const CVec o = lap_site(g, packed_links(U), PackedVec{const_cast<double2*>(p)}, s, diag, c);
+    const CVec o = lap_tile(g, packed_links(U), in, T, diag, c, lds);
+    PackedVec{t}.store(s, o);
+    d = dot_re(c, o);
+  } else if (s < g.V) {
+    CVec c;
+    const CVec o = lap_site(g, packed_links(U), in, s, diag, c);
     PackedVec{t}.store(s, o);
     d = dot_re(c, o);
   }
@@ -190,6 +274,7 @@ __global__ __launch_bounds__(kBlock) void k_lap_packed(Geom g, const void* U, co
 }
 
 // r = b - L x; |r|^2 per workgroup.
+template <bool TILE>
 __global__ __launch_bounds__(kBlock) void k_lap_residual(Geom g, const void* U, const double2* x, const double2* b,
                                                          double2* r, double diag, int gate, SolverState* st,
                                                          double* partials) {
@@ -197,9 +282,17 @@ __global__ __launch_bounds__(kBlock) void k_lap_residual(Geom g, const void* U, 
   const int T = xcd_tile(blockIdx.x, gridDim.x);
   const int s = T * kBlock + threadIdx.x;
   double n2 = 0.0;
-  if (s < g.V) {
-    CVec c;
-    const CVec lx = lap_site(g, packed_links(U), PackedVec{const_cast<double2*>(x)}, s, diag, c);
+  const PackedVec in{const_cast<double2*>(x)};
+  CVec lx, c;
+  bool have = true;
+  if constexpr (TILE) {
+    __shared__ LapTileLds lds;
+    lx = lap_tile(g, packed_links(U), in, T, diag, c, lds);
+  } else {
+    have = s < g.V;
+    if (have) lx = lap_site(g, packed_links(U), in, s, diag, c);
+  }
+  if (have) {
     CVec o = PackedVec{const_cast<double2*>(b)}.load(s);
 #pragma unroll
     for (int i = 0; i < 6; ++i) o.v[i] -= lx.v[i];
@@ -299,15 +392,25 @@ void launch_lap_unpack(const Geom& g, const void* in, void* out, int c64, hipStr
 
 void launch_lap_packed(const Geom& g, const void* U, const void* p, void* t, double m2, int gate, int fin,
                        SolverState* st, double* partials, hipStream_t s, const EventPair* ev) {
-  launch_lap(k_lap_packed, g, s, ev, g, U, static_cast<const double2*>(p), static_cast<double2*>(t), m2 + 8.0, gate,
-             fin, st, partials);
+  if (g.tiled)
+    launch_lap(k_lap_packed<true>, g, s, ev, g, U, static_cast<const double2*>(p), static_cast<double2*>(t), m2 + 8.0,
+               gate, fin, st, partials);
+  else
+    launch_lap(k_lap_packed<false>, g, s, ev, g, U, static_cast<const double2*>(p), static_cast<double2*>(t), m2 + 8.0,
+               gate, fin, st, partials);
   if (fin != F_NONE) launch_finalize_n(g.nblocks, partials, st, fin, gate, s);
 }
 
 void launch_lap_residual(const Geom& g, const void* U, const void* x, const void* b, void* r, double m2, int gate,
                          int fin, SolverState* st, double* partials, hipStream_t s) {
-  k_lap_residual<<<g.nblocks, kBlock, 0, s>>>(g, U, static_cast<const double2*>(x), static_cast<const double2*>(b),
-                                              static_cast<double2*>(r), m2 + 8.0, gate, st, partials);
+  if (g.tiled)
+    k_lap_residual<true><<<g.nblocks, kBlock, 0, s>>>(g, U, static_cast<const double2*>(x),
+                                                      static_cast<const double2*>(b), static_cast<double2*>(r),
+                                                      m2 + 8.0, gate, st, partials);
+  else
+    k_lap_residual<false><<<g.nblocks, kBlock, 0, s>>>(g, U, static_cast<const double2*>(x),
+                                                       static_cast<const double2*>(b), static_cast<double2*>(r),
+                                                       m2 + 8.0, gate, st, partials);
   launch_finalize_n(g.nblocks, partials, st, fin, gate, s);
 }
 
