@@ -371,6 +371,7 @@ __global__ __launch_bounds__(kBlock) WD_TILED_OCCUPANCY void k_wilson_tiled(Geom
   uint32_t lk[8][9];
   tile_stage<P, C12>(g, T, U, in, lds, lk);
   __syncthreads();
+  tile_links_late<C12>(g, T, U, lk);
   float o[24];
   tile_wilson<P, C12, DAG>(lds, lk, (float)diag, o);
   spinor_of<P>(out).store(T * kTileSites + threadIdx.x, o);
@@ -394,6 +395,7 @@ __global__ __launch_bounds__(kBlock) WD_TILED_OCCUPANCY void k_cg_update_tiled(G
   uint32_t lk[8][9];
   tile_stage<P, C12>(g, T, U, t, lds, lk);
   __syncthreads();
+  tile_links_late<C12>(g, T, U, lk);
   float q[24];
   tile_wilson<P, C12, true>(lds, lk, (float)diag, q);
   const int s = T * kTileSites + threadIdx.x;

@@ -75,25 +75,37 @@ template <bool C12> struct LinkFormat {
   static constexpr int words = 4 * entries;      // per site, 4 directions
 };
 
-// Stage the tile's spinors and halo faces; prefetch the 8 links of site s.
-template <int P, bool C12>
-__device__ __forceinline__ void tile_stage(const Geom& g, int T, const void* Uv, const SpinorBuf& in, TileLds<P>& lds,
-                                           uint32_t lk[8][9]) {
+// Links of directions M0 <= mu < M1 of this thread's site into registers: the
+// forward U_mu(s) in lk[mu], the backward U_mu(s - mu) in lk[4 + mu].
+template <bool C12, int M0, int M1>
+__device__ __forceinline__ void tile_links(const Geom& g, int T, const void* Uv, uint32_t lk[8][9]) {
   constexpr int NE = LinkFormat<C12>::entries;
   constexpr int NW = LinkFormat<C12>::words;
-  const int l = threadIdx.x;
-  const int s = T * kTileSites + l;
+  const int s = T * kTileSites + threadIdx.x;
   const uint32_t* U = static_cast<const uint32_t*>(Uv);
-  const typename SpinorWord<P>::T* src = static_cast<const typename SpinorWord<P>::T*>(in.data);
   const Nbrs nb = neighbours(g, s);
 #pragma unroll
-  for (int mu = 0; mu < 4; ++mu)
+  for (int mu = M0; mu < M1; ++mu)
 #pragma unroll
     for (int e = 0; e < NE; ++e) lk[mu][e] = U[word_index(s, NW, mu * NE + e)];
 #pragma unroll
-  for (int mu = 0; mu < 4; ++mu)
+  for (int mu = M0; mu < M1; ++mu)
 #pragma unroll
     for (int e = 0; e < NE; ++e) lk[4 + mu][e] = U[word_index(nb.bwd[mu], NW, mu * NE + e)];
+}
+
+// Links of the first kEarlyDirs directions are loaded with the tile (before
+// the barrier); the rest after it, so that their latency overlaps the first
+// hops instead of the wait at the barrier.
+constexpr int kEarlyDirs = 2;
+
+// Stage the tile's spinors and halo faces; prefetch the early links of site s.
+template <int P, bool C12>
+__device__ __forceinline__ void tile_stage(const Geom& g, int T, const void* Uv, const SpinorBuf& in, TileLds<P>& lds,
+                                           uint32_t lk[8][9]) {
+  const int l = threadIdx.x;
+  const int s = T * kTileSites + l;
+  const typename SpinorWord<P>::T* src = static_cast<const typename SpinorWord<P>::T*>(in.data);
   stage_slot(lds, l, src, in.scale, s);
   // halo: wavefront mu stages the two mu faces
   const int mu = l >> 6;
@@ -106,6 +118,13 @@ __device__ __forceinline__ void tile_stage(const Geom& g, int T, const void* Uv,
   const int slot_m = kTileSites + (2 * mu + 1) * 64 + f;
   stage_slot(lds, slot_p, src, in.scale, sp);
   stage_slot(lds, slot_m, src, in.scale, sm);
+  tile_links<C12, 0, kEarlyDirs>(g, T, Uv, lk);
+}
+
+// After tile_stage's barrier: the remaining links.
+template <bool C12>
+__device__ __forceinline__ void tile_links_late(const Geom& g, int T, const void* Uv, uint32_t lk[8][9]) {
+  tile_links<C12, kEarlyDirs, 4>(g, T, Uv, lk);
 }
 
 // ---- FP64 / FP32 stencils on the tiled order. A workgroup owns one 4^4
