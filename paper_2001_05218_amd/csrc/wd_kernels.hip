@@ -606,68 +606,80 @@ __global__ __launch_bounds__(kBlock) void k_norm2(Geom g, SpinorBuf v, int gate,
 //   sum_spin ((1-g)a)_s (x) b_s^* = h (x) (b_up - A b_dn)^*  (two colour outer products),
 // and likewise (1 + g): sum_spin b_s (x) ((1+g)a)_s^* = (b_up + A b_dn) (x) h'^*.
 
-template <int MU>
-__device__ __forceinline__ void force_dir(const double a0[24], const double b0[24], const double a1[24],
-                                          const double b1[24], double F[18]) {
-  double h1[12], k1[12], h2[12], k2[12];
-  project<MU, -1>(a0, h1);   // (1 - g) a(x), upper half
-  project<MU, -1>(b1, k1);   // matching combination of b(x + mu)
-  project<MU, +1>(b0, h2);   // (1 + g) b(x)
-  project<MU, +1>(a1, k2);   // (1 + g) a(x + mu)
+// f += sum_{k=0,1} u[k] (x) conj(v[k]) for half spinors u, v (index (k * 3 + c) * 2).
+__device__ __forceinline__ void outer_acc(const double u[12], const double v[12], double f[18]) {
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      double re = 0.0, im = 0.0;
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
-        // u_i conj(v_j)
-        const double ur = h1[(k * 3 + i) * 2], ui = h1[(k * 3 + i) * 2 + 1];
-        const double vr = k1[(k * 3 + j) * 2], vi = k1[(k * 3 + j) * 2 + 1];
-        re += ur * vr + ui * vi;
-        im += ui * vr - ur * vi;
-        const double wr = h2[(k * 3 + i) * 2], wi = h2[(k * 3 + i) * 2 + 1];
-        const double zr = k2[(k * 3 + j) * 2], zi = k2[(k * 3 + j) * 2 + 1];
-        re += wr * zr + wi * zi;
-        im += wi * zr - wr * zi;
+        const double ur = u[(k * 3 + i) * 2], ui = u[(k * 3 + i) * 2 + 1];
+        const double vr = v[(k * 3 + j) * 2], vi = v[(k * 3 + j) * 2 + 1];
+        f[(i * 3 + j) * 2] += ur * vr + ui * vi;
+        f[(i * 3 + j) * 2 + 1] += ui * vr - ur * vi;
       }
-      F[(i * 3 + j) * 2] = re;
-      F[(i * 3 + j) * 2 + 1] = im;
     }
   }
 }
 
+// G_mu at site s (0 outside the lattice), 18 reals. Each of the four spinors is
+// loaded and projected in turn, so at most one full spinor is live.
+template <int MU>
+__device__ __forceinline__ void force_site(const CanonSpinor& a, const CanonSpinor& b, int s, int sf, double f[18]) {
+  double psi[24], h[12], k[12];
+  a.load(s, psi);
+  project<MU, -1>(psi, h);    // (1 - g) a(x), upper half
+  b.load(sf, psi);
+  project<MU, -1>(psi, k);    // matching combination of b(x + mu)
+  outer_acc(h, k, f);
+  b.load(s, psi);
+  project<MU, +1>(psi, h);    // (1 + g) b(x)
+  a.load(sf, psi);
+  project<MU, +1>(psi, k);    // (1 + g) a(x + mu)
+  outer_acc(h, k, f);
+}
+
+// One workgroup: 256 consecutive sites (linear order). For each direction the
+// block's 256 x 9 link entries are staged in LDS and stored as one contiguous,
+// coalesced range of F (a thread's own 144-byte record would otherwise be
+// written as nine 16-byte pieces 144 bytes apart from its neighbours').
+template <int MU>
+__device__ __forceinline__ void force_dir(Geom g, const CanonSpinor& a, const CanonSpinor& b, double c, int accumulate,
+                                          double2* __restrict__ F, int s0, const Nbrs& nb, double2 (*stage)[kBlock]) {
+  const int s = s0 + threadIdx.x;
+  double f[18];
+#pragma unroll
+  for (int i = 0; i < 18; ++i) f[i] = 0.0;
+  if (s < g.V) force_site<MU>(a, b, s, nb.fwd[MU], f);
+#pragma unroll
+  for (int e = 0; e < 9; ++e) stage[e][threadIdx.x] = make_double2(c * f[2 * e], c * f[2 * e + 1]);
+  __syncthreads();
+  const int n = min(kBlock, g.V - s0) * 9;
+  double2* dst = F + ((size_t)MU * g.V + s0) * 9;
+  for (int q = threadIdx.x; q < n; q += kBlock) {
+    double2 v = stage[q % 9][q / 9];
+    if (accumulate) {
+      const double2 o = dst[q];
+      v.x += o.x;
+      v.y += o.y;
+    }
+    dst[q] = v;
+  }
+  __syncthreads();   // the stage is rewritten for the next direction
+}
+
 __global__ __launch_bounds__(kBlock) void k_force(Geom g, CanonSpinor a, CanonSpinor b, double coeff, int accumulate,
                                                   double2* __restrict__ F) {
-  const int s = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  if (s >= g.V) return;
-  const Nbrs nb = neighbours(g, s);
-  double a0[24], b0[24], a1[24], b1[24], f[18];
-  a.load(s, a0);
-  b.load(s, b0);
-#pragma unroll
-  for (int mu = 0; mu < 4; ++mu) {
-    a.load(nb.fwd[mu], a1);
-    b.load(nb.fwd[mu], b1);
-    switch (mu) {
-      case 0: force_dir<0>(a0, b0, a1, b1, f); break;
-      case 1: force_dir<1>(a0, b0, a1, b1, f); break;
-      case 2: force_dir<2>(a0, b0, a1, b1, f); break;
-      default: force_dir<3>(a0, b0, a1, b1, f); break;
-    }
-    double2* dst = F + ((size_t)mu * g.V + s) * 9;
-    const double c = 0.5 * coeff;
-#pragma unroll
-    for (int e = 0; e < 9; ++e) {
-      double2 v = make_double2(c * f[2 * e], c * f[2 * e + 1]);
-      if (accumulate) {
-        const double2 o = dst[e];
-        v.x += o.x;
-        v.y += o.y;
-      }
-      dst[e] = v;
-    }
-  }
+  __shared__ double2 stage[9][kBlock];
+  const int s0 = blockIdx.x * kBlock;
+  const int s = s0 + threadIdx.x;
+  const Nbrs nb = neighbours(g, s < g.V ? s : s0);
+  const double c = 0.5 * coeff;
+  force_dir<0>(g, a, b, c, accumulate, F, s0, nb, stage);
+  force_dir<1>(g, a, b, c, accumulate, F, s0, nb, stage);
+  force_dir<2>(g, a, b, c, accumulate, F, s0, nb, stage);
+  force_dir<3>(g, a, b, c, accumulate, F, s0, nb, stage);
 }
 
 __global__ void k_init_state(SolverState* st, double tol, int interval, double delta, double* hist,
