@@ -310,9 +310,9 @@ __global__ __launch_bounds__(kBlock) void k_wilson_canonical(Geom g, CanonGauge 
   out.store(s, o);
 }
 
-// The stencil at site s of workgroup tile T: from the LDS-staged tile when
-// TILE (FP64 / FP32 on the tiled order; every thread of the workgroup must
-// get here), else straight from memory.
+// The stencil at site s of workgroup tile T: from the LDS-staged tile, each
+// link read once, when TILE (FP64 / FP32 on the tiled order; every thread of
+// the workgroup must get here), else straight from memory.
 template <int P, bool DAG, bool TILE>
 __device__ __forceinline__ void stencil_at(const Geom& g, const void* U, const SpinorBuf& in, int T, int s,
                                            typename PackedSpinor<P>::Real diag,
@@ -320,8 +320,9 @@ __device__ __forceinline__ void stencil_at(const Geom& g, const void* U, const S
   const Nbrs nb = neighbours(g, s);
   if constexpr (TILE) {
     __shared__ typename TileWord<P>::T lds[TileWord<P>::n * kTileSites];
+    __shared__ UpBuf<typename PackedSpinor<P>::Real> up;
     const TileSrc<P> src = stage_own_tile<P>(in, T, lds);
-    wilson_site<DAG>(gauge_of<P>(U), src, s, nb, diag, o);
+    wilson_site_once<DAG>(gauge_of<P>(U), src, s, nb, diag, o, up);
   } else {
     wilson_site<DAG>(gauge_of<P>(U), spinor_of<P>(in), s, nb, diag, o);
   }

@@ -183,6 +183,71 @@ __device__ __forceinline__ TileSrc<P> stage_own_tile(const SpinorBuf& in, int T,
   return t;
 }
 
+// FP64 / FP32 tiles, each link read once. The thread at x loads U_mu(x),
+// applies it to its forward neighbour and, as U_mu(x)^+ times the spin
+// projection of its own spinor, hands the backward term of the site x + mu
+// over through LDS (`up`, one direction at a time, two barriers per
+// direction). Only a thread on the tile's lower mu face loads U_mu(x - mu)
+// itself. Without this, every link is loaded twice (forward at x, backward at
+// x + mu), and the second load mostly misses L2.
+template <typename R> struct UpBuf { R v[12][kTileSites]; };
+
+template <int MU, bool DAG, class Gauge, class Src, typename R>
+__device__ __forceinline__ void hop_dir_once(const Gauge& U, const Src& in, int s, const Nbrs& nb, R acc[24],
+                                             UpBuf<R>& up) {
+  constexpr int SF = DAG ? +1 : -1;
+  constexpr int SB = -SF;
+  constexpr int ls = 1 << (2 * MU);
+  const int l = threadIdx.x;
+  const int lm = (l >> (2 * MU)) & 3;
+  R psi[24], h[12], w[12], u[18];
+  U.load_fwd(s, MU, u);
+  in.load(nb.fwd[MU], psi);
+  project<MU, SF>(psi, h);
+  su3_mul_half<false>(u, h, w);
+  reconstruct_add<MU, SF>(acc, w);
+  if (lm < 3) {
+    in.load(s, psi);
+    project<MU, SB>(psi, h);
+    su3_mul_half<true>(u, h, w);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) up.v[i][l + ls] = w[i];
+  }
+  __syncthreads();
+  if (lm > 0) {
+#pragma unroll
+    for (int i = 0; i < 12; ++i) w[i] = up.v[i][l];
+  } else {
+    in.load(nb.bwd[MU], psi);
+    U.load_bwd(nb.bwd[MU], MU, u);
+    project<MU, SB>(psi, h);
+    su3_mul_half<true>(u, h, w);
+  }
+  reconstruct_add<MU, SB>(acc, w);
+  __syncthreads();   // `up` is rewritten by the next direction
+#pragma unroll
+  for (int i = 0; i < 24; ++i) asm volatile("" : "+v"(acc[i]));
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// out = (m + 4) psi(x) - 1/2 sum_mu hops at site s of the staged tile; every
+// thread of the workgroup must call it (barriers).
+template <bool DAG, class Gauge, class Src, typename R>
+__device__ __forceinline__ void wilson_site_once(const Gauge& U, const Src& in, int s, const Nbrs& nb, R diag,
+                                                 R out[24], UpBuf<R>& up) {
+  R acc[24];
+#pragma unroll
+  for (int i = 0; i < 24; ++i) acc[i] = 0;
+  hop_dir_once<0, DAG>(U, in, s, nb, acc, up);
+  hop_dir_once<1, DAG>(U, in, s, nb, acc, up);
+  hop_dir_once<2, DAG>(U, in, s, nb, acc, up);
+  hop_dir_once<3, DAG>(U, in, s, nb, acc, up);
+  R c[24];
+  in.load(s, c);
+#pragma unroll
+  for (int i = 0; i < 24; ++i) out[i] = fma(diag, c[i], R(-0.5) * acc[i]);
+}
+
 template <int P>
 __device__ __forceinline__ void tile_spinor(const TileLds<P>& lds, int slot, float v[24]) {
   typename SpinorWord<P>::T d[3];
