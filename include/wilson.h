@@ -171,11 +171,14 @@ int cg_solve(const wd_lattice* lat, double mass, const void* U, const void* b, v
 /*
  * Solve nrhs systems sharing one gauge field in ONE persistent cooperative
  * launch. B, X: device, (nrhs, Lt, Lz, Ly, Lx, 4, 3) of element type
- * params->io_dtype. Inner iterations run in FP32 on FP32 fields with every
- * link load reused across all right-hand sides; each system carries its own
- * alpha, beta and convergence mask; FP64 reliable updates every
- * params->reliable_interval iterations recompute each residual from an FP64
- * solution. results: host array of nrhs entries (may be NULL).
+ * params->io_dtype. Inner iterations run in FP32 arithmetic with every link
+ * load (FP32 links) reused across all right-hand sides; p, r and t are stored
+ * in params->inner_prec (WD_F32, WD_BF16, WD_F16 or WD_I8; WD_F64 is rejected)
+ * and the solution increment in FP32. Each system carries its own alpha, beta
+ * and convergence mask; FP64 reliable updates (every
+ * params->reliable_interval iterations, and whenever a system's residual has
+ * fallen by params->inner_tol, default as for cg_solve) recompute each
+ * residual from an FP64 solution. results: host array of nrhs entries (may be NULL).
  * 1 <= nrhs <= 16. Blocks until all systems end. Returns WD_OK if every
  * system converged, WD_NOT_CONVERGED if any did not, or a WD_ERR_* code.
  */

@@ -273,7 +273,7 @@ int validate_params(const wd_cg_params* p) {
 // The documented workspace size: for nrhs = 1 it covers both cg_solve and a
 // single-system cg_solve_batched.
 size_t required_bytes(const Geom& g, const wd_cg_params* p, int nrhs) {
-  const size_t batched = batched_workspace_bytes(g, nrhs, p->history_len);
+  const size_t batched = batched_workspace_bytes(g, nrhs, p->history_len, p->inner_prec);
   if (nrhs == 1)
     return std::max(layout_cg(nullptr, g, p->inner_prec, p->history_len, ring_length(p, g)).bytes, batched);
   return batched;
@@ -875,8 +875,9 @@ extern "C" int cg_solve_batched(const wd_lattice* lat, double mass, const void* 
   if (rc) return rc;
   if ((rc = validate_params(params))) return rc;
   if (nrhs < 1 || nrhs > 16) return fail(WD_ERR_INVALID, "nrhs = %d must be in 1..16", nrhs);
-  if (params->inner_prec != WD_F32)
-    return fail(WD_ERR_INVALID, "batched solves run FP32 inner iterations: inner_prec must be WD_F32");
+  if (params->inner_prec == WD_F64)
+    return fail(WD_ERR_INVALID, "batched solves run FP32 inner iterations: inner_prec must be WD_F32, WD_BF16, "
+                                "WD_F16 or WD_I8");
   if (!U || !B || !X) return fail(WD_ERR_INVALID, "NULL field pointer");
   if (B == X) return fail(WD_ERR_INVALID, "B and X must not alias");
   if (!std::isfinite(mass)) return fail(WD_ERR_INVALID, "mass is not finite");

@@ -1,7 +1,9 @@
 // Batched multi-RHS conjugate gradient in one persistent cooperative launch.
 //
 // Up to 16 right-hand sides share one gauge field. Inner iterations run in
-// FP32 on FP32 fields; every few iterations (and whenever an inner residual
+// FP32 arithmetic on p, r and t stored in FP32, BF16, FP16 (+ per-site scale)
+// or int8 fixed point (the template parameter P), with the solution
+// increment in FP32; every few iterations (and whenever an inner residual
 // has dropped by a fixed factor or reached the target) an FP64 reliable
 // update flushes the FP32 solution increment into the FP64 solution and
 // recomputes that system's residual exactly -- the two-precision scheme of
@@ -47,10 +49,15 @@ struct BatchArgs {
   double diag;        // m + 4
   const float2* U32;  // packed FP32 links
   const double2* U64; // packed FP64 links
-  char* p;            // FP32 vectors, right-hand side k at base + k * stride32
+  char* p;            // inner-storage vectors, right-hand side k at base + k * strideL
   char* r;
   char* t;
-  char* xh;
+  char* ps;           // their per-site scales (FP16, int8), at base + k * strideS; else null
+  char* rs;
+  char* ts;
+  size_t strideL;
+  size_t strideS;
+  char* xh;           // FP32 solution increment, right-hand side k at base + k * stride32
   char* x64;          // FP64 vectors, right-hand side k at base + k * stride64
   char* b64;
   char* t64;
@@ -90,6 +97,13 @@ __device__ __forceinline__ PackedSpinor<P_F32> f32_of(char* base, size_t stride,
   PackedSpinor<P_F32> s;
   s.data = reinterpret_cast<float4*>(base + (size_t)k * stride);
   s.scale = nullptr;
+  return s;
+}
+template <int P>
+__device__ __forceinline__ PackedSpinor<P> low_of(char* base, char* sbase, const BatchArgs& a, int k) {
+  PackedSpinor<P> s;
+  s.data = reinterpret_cast<decltype(s.data)>(base + (size_t)k * a.strideL);
+  s.scale = sbase ? reinterpret_cast<float*>(sbase + (size_t)k * a.strideS) : nullptr;
   return s;
 }
 __device__ __forceinline__ PackedSpinor<P_F64> f64_of(char* base, size_t stride, int k) {
@@ -158,6 +172,7 @@ __device__ __forceinline__ void stage_links(const BatchArgs& a, int s, bool vali
   __syncthreads();
 }
 
+template <int P>
 __global__ __launch_bounds__(kBlock) void k_batched_cg(BatchArgs a) {
   cgrp::grid_group grid = cgrp::this_grid();
   __shared__ float2 lds_fwd[36][64];
@@ -263,7 +278,7 @@ __global__ __launch_bounds__(kBlock) void k_batched_cg(BatchArgs a) {
             n2[j] += d * d;
             rv[i] = (float)d;
           }
-          f32_of(a.r, a.stride32, k).store(s, rv);
+          low_of<P>(a.r, a.rs, a, k).store(s, rv);
         }
       }
     }
@@ -288,8 +303,8 @@ __global__ __launch_bounds__(kBlock) void k_batched_cg(BatchArgs a) {
             const int k = wave + kWaves * j;
             if (k >= nrhs || !sc.active[k]) continue;
             float o[24];
-            wilson_site<false>(lg, f32_of(a.p, a.stride32, k), s, nb, diag, o);
-            f32_of(a.t, a.stride32, k).store(s, o);
+            wilson_site<false>(lg, low_of<P>(a.p, a.ps, a, k), s, nb, diag, o);
+            low_of<P>(a.t, a.ts, a, k).store(s, o);
 #pragma unroll
             for (int i = 0; i < 24; ++i) n2[j] += (double)o[i] * (double)o[i];
           }
@@ -325,20 +340,30 @@ __global__ __launch_bounds__(kBlock) void k_batched_cg(BatchArgs a) {
             const int k = wave + kWaves * j;
             if (k >= nrhs || !sc.active[k]) continue;
             float q[24], rv[24], pv[24], xv[24];
-            wilson_site<true>(lg, f32_of(a.t, a.stride32, k), s, nb, diag, q);
-            const auto R = f32_of(a.r, a.stride32, k);
+            wilson_site<true>(lg, low_of<P>(a.t, a.ts, a, k), s, nb, diag, q);
+            const auto R = low_of<P>(a.r, a.rs, a, k);
             const auto X = f32_of(a.xh, a.stride32, k);
             R.load(s, rv);
-            f32_of(a.p, a.stride32, k).load(s, pv);
+            low_of<P>(a.p, a.ps, a, k).load(s, pv);
             X.load(s, xv);
             const float al = (float)sc.alpha[k];
 #pragma unroll
             for (int i = 0; i < 24; ++i) {
               rv[i] = fmaf(-al, q[i], rv[i]);
               xv[i] = fmaf(al, pv[i], xv[i]);
-              n2[j] += (double)rv[i] * (double)rv[i];
             }
-            R.store(s, rv);
+            if constexpr (P == P_F32) {
+              R.store(s, rv);
+            } else {
+              // store, then take the norm of what the next iteration reads
+              typename SpinorWord<P>::T d[3];
+              float scl;
+              PackedSpinor<P>::pack(rv, d, scl);
+              R.store_raw(s, d, scl);
+              PackedSpinor<P>::unpack(d, scl, rv);
+            }
+#pragma unroll
+            for (int i = 0; i < 24; ++i) n2[j] += (double)rv[i] * (double)rv[i];
             X.store(s, xv);
           }
         }
@@ -403,8 +428,8 @@ __global__ __launch_bounds__(kBlock) void k_batched_cg(BatchArgs a) {
       for (int k = wave; k < nrhs; k += kWaves) {
         if (!sc.active[k]) continue;
         float rv[24], pv[24];
-        const auto Pk = f32_of(a.p, a.stride32, k);
-        f32_of(a.r, a.stride32, k).load(s, rv);
+        const auto Pk = low_of<P>(a.p, a.ps, a, k);
+        low_of<P>(a.r, a.rs, a, k).load(s, rv);
         Pk.load(s, pv);
         const float be = (float)sc.beta[k];
 #pragma unroll
@@ -458,17 +483,20 @@ struct BatchedWorkspace {
   char* p;
   char* r;
   char* t;
+  char* ps;
+  char* rs;
+  char* ts;
   char* xh;
   char* x64;
   char* b64;
   char* t64;
-  size_t stride32, stride64;
+  size_t strideL, strideS, stride32, stride64;
   size_t bytes;
 };
 
 static size_t al256(size_t n) { return (n + 255) & ~size_t(255); }
 
-static BatchedWorkspace layout_batched(void* base, const Geom& g, int nrhs) {
+static BatchedWorkspace layout_batched(void* base, const Geom& g, int nrhs, int prec) {
   BatchedWorkspace w{};
   char* b = static_cast<char*>(base);
   size_t off = 0;
@@ -484,11 +512,18 @@ static BatchedWorkspace layout_batched(void* base, const Geom& g, int nrhs) {
   w.partC = reinterpret_cast<double*>(take(np * sizeof(double)));
   w.U32 = take(gauge_bytes(P_F32, g.Vpad));
   w.U64 = take(gauge_bytes(P_F64, g.Vpad));
+  w.strideL = al256(spinor_bytes(prec, g.Vpad));
+  w.strideS = al256(spinor_scale_bytes(prec, g.Vpad));
   w.stride32 = al256(spinor_bytes(P_F32, g.Vpad));
   w.stride64 = al256(spinor_bytes(P_F64, g.Vpad));
-  w.p = take(w.stride32 * nrhs);
-  w.r = take(w.stride32 * nrhs);
-  w.t = take(w.stride32 * nrhs);
+  w.p = take(w.strideL * nrhs);
+  w.r = take(w.strideL * nrhs);
+  w.t = take(w.strideL * nrhs);
+  if (w.strideS) {
+    w.ps = take(w.strideS * nrhs);
+    w.rs = take(w.strideS * nrhs);
+    w.ts = take(w.strideS * nrhs);
+  }
   w.xh = take(w.stride32 * nrhs);
   w.x64 = take(w.stride64 * nrhs);
   w.b64 = take(w.stride64 * nrhs);
@@ -497,16 +532,26 @@ static BatchedWorkspace layout_batched(void* base, const Geom& g, int nrhs) {
   return w;
 }
 
-size_t batched_workspace_bytes(const Geom& g, int nrhs, int hist_len) {
+// Inner storage of a batched solve: the caller's precision, FP32 for anything
+// the batched kernel does not store (FP64).
+static int batched_prec(int inner) {
+  return (inner == WD_BF16 || inner == WD_F16 || inner == WD_I8) ? inner : P_F32;
+}
+
+size_t batched_workspace_bytes(const Geom& g, int nrhs, int hist_len, int inner_prec) {
   (void)hist_len;
-  return layout_batched(nullptr, g, nrhs).bytes;
+  return layout_batched(nullptr, g, nrhs, batched_prec(inner_prec)).bytes;
 }
 
 int batched_solve(const Geom& g, double mass, const void* U, int nrhs, const void* B, void* X,
                   const wd_cg_params* p, wd_cg_result* res, void* ws, hipStream_t s, char* err, size_t errlen) {
   const auto t0 = std::chrono::steady_clock::now();
-  const BatchedWorkspace w = layout_batched(ws, g, nrhs);
+  const int P = batched_prec(p->inner_prec);
+  const BatchedWorkspace w = layout_batched(ws, g, nrhs, P);
   const int interval = p->reliable_interval > 0 ? p->reliable_interval : 50;
+  // residual reduction between FP64 recomputations, as for single solves
+  double delta = (P == WD_BF16 || P == WD_I8) ? 0.1 : (P == WD_F16) ? 1e-2 : 1e-4;
+  if (p->inner_tol > 0.0) delta = p->inner_tol;
   const int c64 = p->io_dtype == WD_C64;
   const size_t io_elem = c64 ? 8 : 16;
   const size_t io_stride = (size_t)g.V * 12 * io_elem;
@@ -518,12 +563,12 @@ int batched_solve(const Geom& g, double mass, const void* U, int nrhs, const voi
     SpinorBuf b64{w.b64 + k * w.stride64, nullptr, P_F64};
     SpinorBuf t64{w.t64 + k * w.stride64, nullptr, P_F64};
     SpinorBuf x64{w.x64 + k * w.stride64, nullptr, P_F64};
-    SpinorBuf r32{w.r + k * w.stride32, nullptr, P_F32};
-    SpinorBuf p32{w.p + k * w.stride32, nullptr, P_F32};
+    SpinorBuf rl{w.r + k * w.strideL, w.rs ? reinterpret_cast<float*>(w.rs + k * w.strideS) : nullptr, P};
+    SpinorBuf pl{w.p + k * w.strideL, w.ps ? reinterpret_cast<float*>(w.ps + k * w.strideS) : nullptr, P};
     SpinorBuf x32{w.xh + k * w.stride32, nullptr, P_F32};
     const char* bk = static_cast<const char*>(B) + k * io_stride;
     char* xk = static_cast<char*>(X) + k * io_stride;
-    launch_init_state(st, p->tol, interval, 1e-4, nullptr, 0, s);
+    launch_init_state(st, p->tol, interval, delta, nullptr, 0, s);
     if (p->rhs_mode == WD_RHS_SOURCE) {
       launch_pack_spinor(g, bk, c64, t64, s);
       launch_wilson_packed(g, P_F64, w.U64, t64, b64, mass, 1, G_ALWAYS, F_NONE, st, w.partA, s);
@@ -534,8 +579,8 @@ int batched_solve(const Geom& g, double mass, const void* U, int nrhs, const voi
     if (p->zero_guess) launch_zero(g, x64, G_ALWAYS, st, s);
     else launch_pack_spinor(g, xk, c64, x64, s);
     launch_wilson_packed(g, P_F64, w.U64, x64, t64, mass, 0, G_ALWAYS, F_NONE, st, w.partA, s);
-    launch_residual(g, w.U64, t64, b64, r32, mass, G_ALWAYS, F_RHO_INIT, st, w.partA, s);
-    launch_convert(g, r32, p32, G_ALWAYS, st, s);
+    launch_residual(g, w.U64, t64, b64, rl, mass, G_ALWAYS, F_RHO_INIT, st, w.partA, s);
+    launch_convert(g, rl, pl, G_ALWAYS, st, s);
     launch_zero(g, x32, G_ALWAYS, st, s);
   }
   hipError_t e = hipGetLastError();
@@ -553,18 +598,24 @@ int batched_solve(const Geom& g, double mass, const void* U, int nrhs, const voi
   a.U32 = static_cast<const float2*>(w.U32);
   a.U64 = static_cast<const double2*>(w.U64);
   a.p = w.p; a.r = w.r; a.t = w.t; a.xh = w.xh;
+  a.ps = w.ps; a.rs = w.rs; a.ts = w.ts;
+  a.strideL = w.strideL;
+  a.strideS = w.strideS;
   a.x64 = w.x64; a.b64 = w.b64; a.t64 = w.t64;
   a.stride32 = w.stride32;
   a.stride64 = w.stride64;
   a.st = w.st;
   a.partA = w.partA; a.partB = w.partB; a.partC = w.partC;
 
+  const void* kernel = P == WD_BF16 ? reinterpret_cast<const void*>(k_batched_cg<P_BF16>)
+                       : P == WD_F16 ? reinterpret_cast<const void*>(k_batched_cg<P_F16>)
+                       : P == WD_I8  ? reinterpret_cast<const void*>(k_batched_cg<P_I8>)
+                                     : reinterpret_cast<const void*>(k_batched_cg<P_F32>);
   int dev = 0, cus = 0, per_cu = 0, coop = 0;
   if ((e = hipGetDevice(&dev)) != hipSuccess ||
       (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess ||
       (e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev)) != hipSuccess ||
-      (e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_batched_cg),
-                                                        kBlock, 0)) != hipSuccess) {
+      (e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0)) != hipSuccess) {
     snprintf(err, errlen, "device query: %s", hipGetErrorString(e));
     return WD_ERR_HIP;
   }
@@ -575,7 +626,7 @@ int batched_solve(const Geom& g, double mass, const void* U, int nrhs, const voi
   int grid = std::min(per_cu * cus, kMaxGrid);
   grid = std::max(1, std::min(grid, a.nsb));
   void* args[] = {&a};
-  e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_batched_cg), dim3(grid), dim3(kBlock), args, 0, s);
+  e = hipLaunchCooperativeKernel(kernel, dim3(grid), dim3(kBlock), args, 0, s);
   if (e != hipSuccess) {
     snprintf(err, errlen, "hipLaunchCooperativeKernel(grid=%d): %s", grid, hipGetErrorString(e));
     return WD_ERR_HIP;

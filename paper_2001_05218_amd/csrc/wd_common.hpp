@@ -369,7 +369,11 @@ template <> struct PackedSpinor<P_F16> {
     float m = 0.f;
 #pragma unroll
     for (int i = 0; i < 24; ++i) m = fmaxf(m, fabsf(v[i]));
-    const float inv = (m > 0.f) ? 1.0f / m : 0.f;
+    // 1 / m overflows for m below ~3e-39 (an FP32 denormal; such sites occur
+    // far from a point source): capped, 0 stays 0 instead of 0 * inf = NaN and
+    // the stored values come out too small by at most m, far below FP32
+    // resolution of any field with a normal-range component.
+    const float inv = (m > 0.f) ? fminf(1.0f / m, 3.4e38f) : 0.f;
     sc = m;
 #pragma unroll
     for (int w = 0; w < 3; ++w) {
@@ -428,7 +432,7 @@ template <> struct PackedSpinor<P_I8> {
       m = fmaxf(m, fabsf(v[i]));
       chk = fmaf(v[i], 0.f, chk);   // NaN if any component is NaN or Inf
     }
-    const float inv = (m > 0.f) ? 127.0f / m : 0.f;
+    const float inv = (m > 0.f) ? fminf(127.0f / m, 3.4e38f) : 0.f;   // capped as for FP16
     sc = (chk == 0.f) ? m : __builtin_nanf("");
 #pragma unroll
     for (int w = 0; w < 3; ++w) {

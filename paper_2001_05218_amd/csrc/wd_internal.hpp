@@ -159,7 +159,7 @@ void launch_finalize_n(int n, double* partials, SolverState* st, int fin, int ga
 // ||v||^2 -> fin
 void launch_norm2(const Geom& g, SpinorBuf v, int gate, int fin, SolverState* st, double* partials, hipStream_t s);
 // Workspace of the batched persistent solver (wd_batched.hip).
-size_t batched_workspace_bytes(const Geom& g, int nrhs, int hist_len);
+size_t batched_workspace_bytes(const Geom& g, int nrhs, int hist_len, int inner_prec);
 // Batched solve after argument validation; writes a message to err on failure.
 int batched_solve(const Geom& g, double mass, const void* U, int nrhs, const void* B, void* X,
                   const ::wd_cg_params* p, ::wd_cg_result* res, void* ws, hipStream_t s, char* err, size_t errlen);

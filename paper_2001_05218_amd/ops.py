@@ -161,8 +161,10 @@ def cg_solve(U: torch.Tensor, b: torch.Tensor, mass: float, tol: float = 1e-10, 
 
 def cg_solve_batched(U: torch.Tensor, B: torch.Tensor, mass: float, tol: float = 1e-10, max_iter: int = 10000,
                      reliable_interval: int = 50, rhs: str = "source", X0: torch.Tensor | None = None,
-                     workspace: torch.Tensor | None = None, raise_on_nonconvergence: bool = True):
-    """Solve nrhs systems sharing U in one persistent launch. B: (nrhs, Lt, Lz, Ly, Lx, 4, 3)."""
+                     workspace: torch.Tensor | None = None, raise_on_nonconvergence: bool = True,
+                     inner: str = "f32"):
+    """Solve nrhs systems sharing U in one persistent launch. B: (nrhs, Lt, Lz, Ly, Lx, 4, 3).
+    inner: storage of the inner vectors ("f32", "bf16", "f16" or "i8"; FP32 arithmetic)."""
     dims = dims_of_spinor(B)
     if B.dim() != 7:
         raise ValueError("B must be (nrhs, Lt, Lz, Ly, Lx, 4, 3)")
@@ -170,7 +172,7 @@ def cg_solve_batched(U: torch.Tensor, B: torch.Tensor, mass: float, tol: float =
     _need(B, "B", (torch.complex128, torch.complex64))
     _need(U, "U", (torch.complex128,), gauge_shape(dims))
     io = WD_C64 if B.dtype == torch.complex64 else WD_C128
-    params, _ = make_params(tol, max_iter, "f32", reliable_interval, rhs, io, X0 is None, 0)
+    params, _ = make_params(tol, max_iter, inner, reliable_interval, rhs, io, X0 is None, 0)
     X = torch.empty_like(B) if X0 is None else X0.clone()
     need = workspace_bytes(dims, params, nrhs)
     if workspace is None or workspace.numel() < need:

@@ -191,3 +191,14 @@ def test_laplace_rejects_bad_args(lib):
     bad = _params(tol=0.0)
     assert lib.laplace_cg_solve(lat, 0.1, 1, 2, 3, ctypes.byref(bad), None, 4, need, None) == _lib.WD_ERR_INVALID
     assert "tol" in _lib.last_error()
+
+
+def test_batched_rejects_fp64_inner_and_sizes_by_storage(lib):
+    lat = _lat((8, 8, 8, 8))
+    f64 = _params(inner_prec=0)
+    rc = lib.cg_solve_batched(lat, 0.1, 1, 4, 2, 3, ctypes.byref(f64), None, 4, 1 << 40, None)
+    assert rc == _lib.WD_ERR_INVALID
+    assert "inner_prec" in _lib.last_error()
+    sizes = {prec: lib.wd_workspace_bytes(lat, ctypes.byref(_params(inner_prec=prec)), 16) for prec in (1, 2, 3, 4)}
+    # p, r, t shrink with the storage (FP32 > FP16 with scales > BF16 > int8 with scales)
+    assert sizes[1] > sizes[3] > sizes[2] > sizes[4] > 0
