@@ -372,8 +372,13 @@ def main():
     for _ in range(max(1, args.fp64_steps)):
         x64, i64, dt = solve("f64", ws["f64"])
         f64_times.append(dt)
+    def plain_res(xs):
+        # ||b - D x|| / ||b|| of the normal-equation solution (D by the library's kernel)
+        rr = bt - wd.wilson_apply(Ut, xs, MASS)
+        return float(torch.linalg.vector_norm(rr) / torch.linalg.vector_norm(bt))
+
     fp64 = {"seconds": float(np.median(f64_times)), "iterations": i64["iterations"],
-            "true_rel_res": i64["true_rel_res"]}
+            "true_rel_res": i64["true_rel_res"], "rel_res_b_minus_Dx": plain_res(x64)}
     log(f"fp64: {fp64}")
 
     # timed region: K full mixed solves
@@ -506,6 +511,7 @@ def main():
         "mixed_cg": {"seconds": per, "iterations": infos[-1]["iterations"],
                      "two_row_links": bool(infos[-1]["two_row_links"]),
                      "reliable_updates": infos[-1]["reliable_updates"], "true_rel_res": infos[-1]["true_rel_res"],
+                     "rel_res_b_minus_Dx": plain_res(x),
                      "rel_diff_vs_fp64_solution": diff},
         "fp64_cg": fp64,
         "refinement_cg": refinement,
