@@ -99,15 +99,28 @@ __device__ __forceinline__ PackedSpinor<P_F32> f32_of(char* base, size_t stride,
   s.scale = nullptr;
   return s;
 }
+// Inner-storage spinors as a stencil source, fenced per direction (see FencedF64).
 template <int P>
-__device__ __forceinline__ PackedSpinor<P> low_of(char* base, char* sbase, const BatchArgs& a, int k) {
-  PackedSpinor<P> s;
+struct Fenced : PackedSpinor<P> {
+  static constexpr bool kFence = true;
+};
+
+template <int P>
+__device__ __forceinline__ Fenced<P> low_of(char* base, char* sbase, const BatchArgs& a, int k) {
+  Fenced<P> s;
   s.data = reinterpret_cast<decltype(s.data)>(base + (size_t)k * a.strideL);
   s.scale = sbase ? reinterpret_cast<float*>(sbase + (size_t)k * a.strideS) : nullptr;
   return s;
 }
-__device__ __forceinline__ PackedSpinor<P_F64> f64_of(char* base, size_t stride, int k) {
-  PackedSpinor<P_F64> s;
+// FP64 spinors for the reliable update's stencils, with the per-direction
+// fence of hop_dir: without it the compiler hoists all eight neighbours' loads
+// and the whole kernel needs over 400 registers (one wave per SIMD).
+struct FencedF64 : PackedSpinor<P_F64> {
+  static constexpr bool kFence = true;
+};
+
+__device__ __forceinline__ FencedF64 f64_of(char* base, size_t stride, int k) {
+  FencedF64 s;
   s.data = reinterpret_cast<double2*>(base + (size_t)k * stride);
   s.scale = nullptr;
   return s;
@@ -157,6 +170,15 @@ __device__ void publish_parts(double* part, const double n2[kMaxRhs / kWaves], i
   }
 }
 
+// n2[j] += v for a runtime j < 4 without indexing a register array (which
+// would move it to scratch memory).
+__device__ __forceinline__ void add_part(double n2[kMaxRhs / kWaves], int j, double v) {
+  n2[0] += (j == 0) ? v : 0.0;
+  n2[1] += (j == 1) ? v : 0.0;
+  n2[2] += (j == 2) ? v : 0.0;
+  n2[3] += (j == 3) ? v : 0.0;
+}
+
 // Stage the FP32 links of site block sb into LDS.
 __device__ __forceinline__ void stage_links(const BatchArgs& a, int s, bool valid, const Nbrs& nb,
                                             float2 (*fwd)[64], float2 (*bwd)[64]) {
@@ -170,6 +192,35 @@ __device__ __forceinline__ void stage_links(const BatchArgs& a, int s, bool vali
   for (int e = 0; e < 9; ++e)
     bwd[wave * 9 + e][lane] = valid ? a.U32[word_index(sbw, 36, wave * 9 + e)] : make_float2(0.f, 0.f);
   __syncthreads();
+}
+
+// The reliable update's FP64 stencils, kept out of line: inlined into the
+// persistent loop they need over 400 registers (the compiler overlaps them
+// with the surrounding loops), which left room for one wave per SIMD.
+__device__ __noinline__ void reliable_dx(const BatchArgs& a, int s, const Nbrs& nb, int k) {
+  const PackedGauge<P_F64> U64{a.U64};
+  double o[24];
+  wilson_site<false>(U64, f64_of(a.x64, a.stride64, k), s, nb, a.diag, o);
+  f64_of(a.t64, a.stride64, k).store(s, o);
+}
+
+// r = low(b - D^+ t) at site s for right-hand side k; returns ||b - D^+ t||^2 there.
+template <int P>
+__device__ __noinline__ double reliable_res(const BatchArgs& a, int s, const Nbrs& nb, int k) {
+  const PackedGauge<P_F64> U64{a.U64};
+  double q[24], bv[24];
+  float rv[24];
+  wilson_site<true>(U64, f64_of(a.t64, a.stride64, k), s, nb, a.diag, q);
+  f64_of(a.b64, a.stride64, k).load(s, bv);
+  double part = 0.0;
+#pragma unroll
+  for (int i = 0; i < 24; ++i) {
+    const double d = bv[i] - q[i];
+    part += d * d;
+    rv[i] = (float)d;
+  }
+  low_of<P>(a.r, a.rs, a, k).store(s, rv);
+  return part;
 }
 
 template <int P>
@@ -219,7 +270,6 @@ __global__ __launch_bounds__(kBlock) void k_batched_cg(BatchArgs a) {
   __syncthreads();
 
   LdsGauge lg{lds_fwd, lds_bwd, lane};
-  const PackedGauge<P_F64> U64{a.U64};
 
   // FP64 reliable update for the flagged right-hand sides: x += xhat, xhat = 0,
   // r = low(b' - D^+ D x), rho_true = ||b' - D^+ D x||^2.
@@ -252,9 +302,7 @@ __global__ __launch_bounds__(kBlock) void k_batched_cg(BatchArgs a) {
         const Nbrs nb = neighbours(a.g, s);
         for (int k = wave; k < nrhs; k += kWaves) {
           if (!sc.flag[k]) continue;
-          double o[24];
-          wilson_site<false>(U64, f64_of(a.x64, a.stride64, k), s, nb, a.diag, o);
-          f64_of(a.t64, a.stride64, k).store(s, o);
+          reliable_dx(a, s, nb, k);
         }
       }
     }
@@ -264,21 +312,11 @@ __global__ __launch_bounds__(kBlock) void k_batched_cg(BatchArgs a) {
       const int s = sb * 64 + lane;
       if (s < a.g.V) {
         const Nbrs nb = neighbours(a.g, s);
-#pragma unroll
+#pragma unroll 1
         for (int j = 0; j < kMaxRhs / kWaves; ++j) {
           const int k = wave + kWaves * j;
           if (k >= nrhs || !sc.flag[k]) continue;
-          double q[24], bv[24];
-          float rv[24];
-          wilson_site<true>(U64, f64_of(a.t64, a.stride64, k), s, nb, a.diag, q);
-          f64_of(a.b64, a.stride64, k).load(s, bv);
-#pragma unroll
-          for (int i = 0; i < 24; ++i) {
-            const double d = bv[i] - q[i];
-            n2[j] += d * d;
-            rv[i] = (float)d;
-          }
-          low_of<P>(a.r, a.rs, a, k).store(s, rv);
+          add_part(n2, j, reliable_res<P>(a, s, nb, k));
         }
       }
     }
@@ -298,15 +336,17 @@ __global__ __launch_bounds__(kBlock) void k_batched_cg(BatchArgs a) {
         if (valid) nb = neighbours(a.g, s);
         stage_links(a, s, valid, nb, lds_fwd, lds_bwd);
         if (valid) {
-#pragma unroll
+#pragma unroll 1
           for (int j = 0; j < kMaxRhs / kWaves; ++j) {
             const int k = wave + kWaves * j;
             if (k >= nrhs || !sc.active[k]) continue;
             float o[24];
             wilson_site<false>(lg, low_of<P>(a.p, a.ps, a, k), s, nb, diag, o);
             low_of<P>(a.t, a.ts, a, k).store(s, o);
+            double part = 0.0;
 #pragma unroll
-            for (int i = 0; i < 24; ++i) n2[j] += (double)o[i] * (double)o[i];
+            for (int i = 0; i < 24; ++i) part += (double)o[i] * (double)o[i];
+            add_part(n2, j, part);
           }
         }
       }
@@ -335,7 +375,7 @@ __global__ __launch_bounds__(kBlock) void k_batched_cg(BatchArgs a) {
         if (valid) nb = neighbours(a.g, s);
         stage_links(a, s, valid, nb, lds_fwd, lds_bwd);
         if (valid) {
-#pragma unroll
+#pragma unroll 1
           for (int j = 0; j < kMaxRhs / kWaves; ++j) {
             const int k = wave + kWaves * j;
             if (k >= nrhs || !sc.active[k]) continue;
@@ -362,8 +402,10 @@ __global__ __launch_bounds__(kBlock) void k_batched_cg(BatchArgs a) {
               R.store_raw(s, d, scl);
               PackedSpinor<P>::unpack(d, scl, rv);
             }
+            double part = 0.0;
 #pragma unroll
-            for (int i = 0; i < 24; ++i) n2[j] += (double)rv[i] * (double)rv[i];
+            for (int i = 0; i < 24; ++i) part += (double)rv[i] * (double)rv[i];
+            add_part(n2, j, part);
             X.store(s, xv);
           }
         }

@@ -376,22 +376,15 @@ __device__ __forceinline__ void su3_third_row_h(uint32_t u[9]) {
 
 // acc += f * reconstruction of (U h) or (U^+ h), h the spin projection of the
 // staged neighbour in `slot`, f its value factor.
+// acc += f * reconstruction of (U h) or (U^+ h): h the spin projection of the
+// half2 spinor words psi (index spin * 3 + colour), U the FP16 link words raw
+// (rows 0 and 1 when C12), f the spinor's value factor.
 template <int MU, int S, bool ADJ, bool C12>
-__device__ __forceinline__ void hop_h(const TileLds<P_I8>& lds, int slot, const uint32_t raw[9], float acc[24]) {
+__device__ __forceinline__ void hop_h_words(const uint32_t psi[12], float f, const uint32_t raw[9], float acc[24]) {
   using T = SpinTab<MU>;
   constexpr int sh = (S > 0) ? 0 : 2;
   constexpr int N0 = (T::n0 + sh) & 3, N1 = (T::n1 + sh) & 3;
   constexpr int FA = ADJ ? 0 : 1, FB = ADJ ? 3 : 2;
-  uint32_t psi[12];
-#pragma unroll
-  for (int w = 0; w < 3; ++w) {
-    const uint4 d = lds.h[w][slot];
-    psi[4 * w] = d.x;
-    psi[4 * w + 1] = d.y;
-    psi[4 * w + 2] = d.z;
-    psi[4 * w + 3] = d.w;
-  }
-  const float f = lds.f[slot];
   uint32_t ha[6], hb[6];   // forms of the projection, index spin row * 3 + colour
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -425,6 +418,21 @@ __device__ __forceinline__ void hop_h(const TileLds<P_I8>& lds, int slot, const 
     }
   }
   reconstruct_fma<MU, S>(acc, w, f);
+}
+
+// The same for a staged int8 slot.
+template <int MU, int S, bool ADJ, bool C12>
+__device__ __forceinline__ void hop_h(const TileLds<P_I8>& lds, int slot, const uint32_t raw[9], float acc[24]) {
+  uint32_t psi[12];
+#pragma unroll
+  for (int w = 0; w < 3; ++w) {
+    const uint4 d = lds.h[w][slot];
+    psi[4 * w] = d.x;
+    psi[4 * w + 1] = d.y;
+    psi[4 * w + 2] = d.z;
+    psi[4 * w + 3] = d.w;
+  }
+  hop_h_words<MU, S, ADJ, C12>(psi, lds.f[slot], raw, acc);
 }
 
 template <bool C12, int MU, bool DAG>
