@@ -1,4 +1,6 @@
-// LDS-staged Wilson stencil for 16-bit fields in the tiled site order.
+// LDS-staged Wilson stencils in the tiled site order: 16- and 8-bit fields
+// (tile plus halo faces in LDS), FP64/FP32 fields (own tile in LDS, each link
+// read once).
 //
 // The paper keeps the inputs of neighbouring stencils on chip in cyclic
 // buffers so that each datum crosses the memory interface once (Sec. 2).
@@ -8,8 +10,9 @@
 // cache-only stencil are ~10 %. Here a workgroup owns one 4^4 tile and
 //   1. issues, all at once, the loads of its 256 spinors plus the 8 halo
 //      faces (64 sites each, read from the neighbouring tiles) into LDS, and
-//      of its sites' 8 links (4 own, 4 backward) into registers;
-//   2. after one barrier evaluates all 8 hops from LDS and registers.
+//      of half of its sites' 8 links (4 own, 4 backward) into registers;
+//   2. after one barrier loads the other half of the links and evaluates all
+//      8 hops from LDS and registers.
 // A workgroup's loads are thus in flight together; the faces it reads are the
 // interiors of tiles that neighbouring workgroups of the same XCD stage at the
 // same moment, so they are served by that XCD's L2.
