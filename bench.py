@@ -252,25 +252,34 @@ def bench_force(dev, a, b, reps=20):
 
 def bench_autograd(dev):
     """Differentiable solve on 16^3x32 (links exp(i 0.3 H), m = 0.1): loss = Re phi^+ chi,
-    chi = (D^+D)^{-1} phi; forward + backward (adjoint solve, 2 D, 2 force kernels)."""
+    chi = (D^+D)^{-1} phi; forward + backward (adjoint solve, 2 D, 2 force kernels),
+    with FP64 and with mixed int8 solves (both to tol 1e-10 in FP64)."""
     import torch
     import fieldgen
     import paper_2001_05218_amd as wd
     dims = (16, 16, 16, 32)
     U = torch.from_numpy(fieldgen.gauge_field(dims, "near_identity", 200105258, eps=0.3)).to(dev)
     phi = torch.from_numpy(fieldgen.gaussian_spinor(dims, 200105259)).to(dev)
-    times = []
-    for _ in range(3):
-        Ug = U.clone().requires_grad_(True)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        chi = wd.wilson_solve(Ug, phi, 0.1, tol=1e-10)
-        loss = (phi.conj() * chi).real.sum()
-        loss.backward()
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t)
-    return {"seconds": min(times), "lattice_xyzt": list(dims), "mass": 0.1, "tol": 1e-10,
-            "note": "forward solve + adjoint solve + 2 D + 2 force kernels, FP64"}
+    variants = {}
+    grads = {}
+    for inner in ("f64", "i8"):
+        times = []
+        for _ in range(3):
+            Ug = U.clone().requires_grad_(True)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            chi = wd.wilson_solve(Ug, phi, 0.1, tol=1e-10, inner=inner)
+            loss = (phi.conj() * chi).real.sum()
+            loss.backward()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t)
+        variants[inner] = {"seconds": min(times)}
+        grads[inner] = Ug.grad
+    gdiff = float(torch.linalg.vector_norm(grads["i8"] - grads["f64"]) / torch.linalg.vector_norm(grads["f64"]))
+    best = min(variants, key=lambda k: variants[k]["seconds"])
+    return {"seconds": variants[best]["seconds"], "inner": best, "variants": variants,
+            "rel_diff_grad_i8_vs_f64": gdiff, "lattice_xyzt": list(dims), "mass": 0.1, "tol": 1e-10,
+            "note": "forward solve + adjoint solve + 2 D + 2 force kernels"}
 
 
 # Laplacian CG (FP64) on the benchmark's links: per iteration and site the

@@ -114,3 +114,20 @@ def test_full_lattice_gradient_vs_oracle_16x16x16x32():
     assert oracle.true_relative_residual(U, chi_n, phi, mass, rhs="normal") <= 1e-12
     gU_r = 2.0 * oracle.force_G(oracle.wilson_D(U, chi_n, mass), chi_n)
     assert rel(to_np(gU), gU_r) <= 1e-10
+
+
+def test_autograd_mixed_inner_matches_fp64():
+    # the differentiable solve with int8-storage inner iterations: both solves
+    # reach the same FP64 tolerance, so the gradient agrees with the FP64 one
+    dims, mass = (8, 8, 8, 8), 0.1
+    U = to_dev(fieldgen.gauge_field(dims, "near_identity", 61, eps=0.3))
+    phi = to_dev(fieldgen.gaussian_spinor(dims, 62))
+    grads = {}
+    for inner in ("f64", "i8"):
+        Ug = U.clone().requires_grad_(True)
+        chi = wd.wilson_solve(Ug, phi, mass, tol=1e-11, inner=inner)
+        (phi.conj() * chi).real.sum().backward()
+        grads[inner] = to_np(Ug.grad)
+    # each solution is within cond(D^+D) * tol <= ((m + 8) / m)^2 * 1e-11 of the
+    # exact one; the gradient is bilinear in chi and lambda
+    assert rel(grads["i8"], grads["f64"]) <= 4 * ((mass + 8) / mass) ** 2 * 1e-11
