@@ -506,10 +506,16 @@ int cg_setup(const Geom& g, double mass, const void* U, const void* b, void* x, 
     launch_pack_spinor(g, b, c64, w.b64, s);
   }
   launch_norm2(g, w.b64, G_ALWAYS, F_BNORM, w.st, w.partials, s);
-  if (p->zero_guess) launch_zero(g, w.x64, G_ALWAYS, w.st, s);
-  else launch_pack_spinor(g, x, c64, w.x64, s);
-  launch_wilson_packed(g, P_F64, w.U64, w.x64, w.t64, mass, 0, G_ALWAYS, F_NONE, w.st, w.partials, s);
-  launch_residual(g, w.U64, w.t64, w.b64, rout, mass, G_ALWAYS, F_RHO_INIT, w.st, w.partials, s);
+  if (p->zero_guess) {
+    // x = 0: the initial residual is b' itself (D 0 = 0 exactly), no stencils
+    launch_zero(g, w.x64, G_ALWAYS, w.st, s);
+    launch_norm2(g, w.b64, G_ALWAYS, F_RHO_INIT, w.st, w.partials, s);
+    launch_convert(g, w.b64, rout, G_ALWAYS, w.st, s);
+  } else {
+    launch_pack_spinor(g, x, c64, w.x64, s);
+    launch_wilson_packed(g, P_F64, w.U64, w.x64, w.t64, mass, 0, G_ALWAYS, F_NONE, w.st, w.partials, s);
+    launch_residual(g, w.U64, w.t64, w.b64, rout, mass, G_ALWAYS, F_RHO_INIT, w.st, w.partials, s);
+  }
   HIP_TRY(hipGetLastError());
   return WD_OK;
 }

@@ -618,10 +618,16 @@ int batched_solve(const Geom& g, double mass, const void* U, int nrhs, const voi
       launch_pack_spinor(g, bk, c64, b64, s);
     }
     launch_norm2(g, b64, G_ALWAYS, F_BNORM, st, w.partA, s);
-    if (p->zero_guess) launch_zero(g, x64, G_ALWAYS, st, s);
-    else launch_pack_spinor(g, xk, c64, x64, s);
-    launch_wilson_packed(g, P_F64, w.U64, x64, t64, mass, 0, G_ALWAYS, F_NONE, st, w.partA, s);
-    launch_residual(g, w.U64, t64, b64, rl, mass, G_ALWAYS, F_RHO_INIT, st, w.partA, s);
+    if (p->zero_guess) {
+      // x = 0: the initial residual is b' itself, no stencils
+      launch_zero(g, x64, G_ALWAYS, st, s);
+      launch_norm2(g, b64, G_ALWAYS, F_RHO_INIT, st, w.partA, s);
+      launch_convert(g, b64, rl, G_ALWAYS, st, s);
+    } else {
+      launch_pack_spinor(g, xk, c64, x64, s);
+      launch_wilson_packed(g, P_F64, w.U64, x64, t64, mass, 0, G_ALWAYS, F_NONE, st, w.partA, s);
+      launch_residual(g, w.U64, t64, b64, rl, mass, G_ALWAYS, F_RHO_INIT, st, w.partA, s);
+    }
     launch_convert(g, rl, pl, G_ALWAYS, st, s);
     launch_zero(g, x32, G_ALWAYS, st, s);
   }
