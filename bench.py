@@ -43,6 +43,11 @@ TOL = 1e-10
 BYTES_PER_SITE = {"f64": 4 * 9 * 16 + 2 * 192, "f32": 4 * 9 * 8 + 2 * 96, "bf16": 4 * 9 * 4 + 2 * 48,
                   "f16": 4 * 9 * 4 + 2 * 48 + 2 * 4, "i8": 4 * 9 * 4 + 2 * 24 + 2 * 4}
 FLOPS_PER_SITE = 1368
+# The paper's own figure (Sec. 5), quoted as context: other hardware, FP32,
+# lattice size and flop count not stated, so it is no target for this workload.
+PAPER_CONTEXT = {"value": 607, "unit": "GFLOP/s", "precision": "FP32",
+                 "hardware": "Xilinx Alveo U280 FPGA card, three kernel instances at 300 MHz, initiation interval 2",
+                 "note": "sustained CG rate reported by the paper; lattice, flop convention and tolerance not stated"}
 # algorithmic bytes per site of the inner loop's kernels, by storage:
 #   D p       : 4 links + p in + t out
 #   update    : 4 links + t in (D^+ t) + r in/out
@@ -525,6 +530,11 @@ def main():
         "fp64_cg": fp64,
         "refinement_cg": refinement,
         "speedup_mixed_vs_fp64": fp64["seconds"] / per,
+        # inner-loop stencils only (two per CG iteration, 1368 flop per site each)
+        "stencil_TFLOP_per_s": {
+            "mixed": 2 * infos[-1]["iterations"] * FLOPS_PER_SITE * V / per / 1e12,
+            "fp64": 2 * fp64["iterations"] * FLOPS_PER_SITE * V / fp64["seconds"] / 1e12},
+        "paper_context": PAPER_CONTEXT,
         "variants": variants,
         "dslash": dsl,
         "roofline": {"bound": "hbm", "kernel": kern["kernel"], "achieved": kern["GB_per_s"],
