@@ -223,8 +223,13 @@ __device__ __noinline__ double reliable_res(const BatchArgs& a, int s, const Nbr
   return part;
 }
 
+// FP16 and int8 storage (whose packing needs a few more registers) are held
+// to two waves per SIMD: left alone the compiler takes 258-259 registers
+// (256 VGPRs and 2-3 AGPRs) and runs one wave, 17-20 % slower. FP32 and BF16
+// fit two waves by themselves.
 template <int P>
-__global__ __launch_bounds__(kBlock) void k_batched_cg(BatchArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((P == P_F16 || P == P_I8) ? 2 : 1, 8)))
+void k_batched_cg(BatchArgs a) {
   cgrp::grid_group grid = cgrp::this_grid();
   __shared__ float2 lds_fwd[36][64];
   __shared__ float2 lds_bwd[36][64];
