@@ -111,7 +111,19 @@ typedef struct {
   double inner_tol;          /* residual reduction between FP64 recomputations; 0 -> the default
                                 (reliable updates: 0.1 BF16 and I8, 1e-2 FP16, 1e-4 FP32;
                                 refinement: 0.1) */
+  int32_t batch_schedule;    /* cg_solve_batched only: WD_BATCH_AUTO, WD_BATCH_PERSISTENT or
+                                WD_BATCH_LOCKSTEP (see below) */
 } wd_cg_params;
+
+/* How cg_solve_batched runs its systems.
+   WD_BATCH_PERSISTENT: one cooperative persistent launch for the whole solve, with
+     per-system convergence masks; every storage precision and lattice.
+   WD_BATCH_LOCKSTEP: the single-system mixed solver's kernels, each CG step one launch
+     over all systems (workgroups of one tile and all systems run back to back, so each
+     link is read from HBM once per step for all of them); BF16, FP16 or int8 storage,
+     reliable updates, every lattice extent a multiple of 4.
+   WD_BATCH_AUTO (0): lockstep where it applies, persistent otherwise. */
+enum { WD_BATCH_AUTO = 0, WD_BATCH_PERSISTENT = 1, WD_BATCH_LOCKSTEP = 2 };
 
 typedef struct {
   int32_t iterations;        /* iterations performed (inner iterations for mixed) */

@@ -20,6 +20,7 @@ WD_RHS_SOURCE, WD_RHS_NORMAL = 0, 1
 WD_C128, WD_C64 = 0, 1
 WD_TWO_ROW_LINKS = 0x100
 WD_RELIABLE_UPDATE, WD_ITERATIVE_REFINEMENT = 0, 1
+WD_BATCH_AUTO, WD_BATCH_PERSISTENT, WD_BATCH_LOCKSTEP = 0, 1, 2
 WD_OK, WD_NOT_CONVERGED = 0, 1
 WD_ERR_INVALID, WD_ERR_HIP, WD_ERR_BREAKDOWN, WD_ERR_NAN, WD_ERR_WORKSPACE = -1, -2, -3, -4, -5
 
@@ -47,6 +48,7 @@ class WdCgParams(ctypes.Structure):
         ("scheme", ctypes.c_int32),
         ("ring_len", ctypes.c_int32),
         ("inner_tol", ctypes.c_double),
+        ("batch_schedule", ctypes.c_int32),
     ]
 
 

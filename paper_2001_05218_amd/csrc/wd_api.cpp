@@ -154,6 +154,99 @@ CgWorkspace layout_cg(void* base, const Geom& g, int inner, int hist_len, int ri
   return w;
 }
 
+// ---- lockstep batched solver (WD_BATCH_LOCKSTEP): the shared gauge copies,
+// a contiguous copy of the systems' states for the host, then one region per
+// system (the single-system layout without the gauge fields) at a fixed stride.
+constexpr int kMaxBatch = 16;
+
+struct LockstepWorkspace {
+  void* U64;
+  void* Ulow;
+  SolverState* states;
+  CgWorkspace sys0;    // system 0; its U64 / Ulow are the shared copies
+  long long stride;    // bytes from one system's region to the next
+  size_t bytes;
+};
+
+// Ring slots per system: the single-system rule with the memory budget shared.
+int ring_length_batch(const wd_cg_params* p, const Geom& g, int nrhs) {
+  if (p->ring_len > 0) return p->ring_len;
+  const size_t per = align_up(spinor_bytes(p->inner_prec, g.Vpad)) + align_up(spinor_scale_bytes(p->inner_prec, g.Vpad));
+  const long long by_mem = (long long)(kRingBudget / ((size_t)nrhs * per));
+  const long long want = std::min<long long>((long long)reliable_interval_of(p) + kSlotEvery, by_mem);
+  return (int)std::max<long long>(8, std::min<long long>(256, want));
+}
+
+LockstepWorkspace layout_lockstep(void* base, const Geom& g, int inner, int ring_len, int nrhs) {
+  Carver c(base);
+  LockstepWorkspace L{};
+  L.U64 = c.take(gauge_bytes(P_F64, g.Vpad));
+  L.Ulow = c.take(gauge_bytes(inner, g.Vpad));
+  L.states = static_cast<SolverState*>(c.take(sizeof(SolverState) * kMaxBatch));
+  const size_t start = c.off;
+  CgWorkspace& w = L.sys0;
+  w.st = static_cast<SolverState*>(c.take(sizeof(SolverState)));
+  w.partials = static_cast<double*>(c.take(sizeof(double) * (size_t)g.nblocks));
+  w.hist = static_cast<double*>(c.take(sizeof(double)));
+  w.b64 = take_spinor(c, P_F64, g);
+  w.x64 = take_spinor(c, P_F64, g);
+  w.t64 = take_spinor(c, P_F64, g);
+  w.rh = take_spinor(c, inner, g);
+  w.th = take_spinor(c, inner, g);
+  w.alpha_hist = static_cast<double*>(c.take(sizeof(double) * (size_t)ring_len));
+  w.ring.prec = inner;
+  w.ring.len = ring_len;
+  w.ring.stride = (long long)align_up(spinor_bytes(inner, g.Vpad));
+  w.ring.data = static_cast<char*>(c.take((size_t)w.ring.stride * ring_len));
+  if (spinor_scale_bytes(inner, g.Vpad)) {
+    w.ring.scale_stride = (long long)align_up(spinor_scale_bytes(inner, g.Vpad));
+    w.ring.scale = static_cast<char*>(c.take((size_t)w.ring.scale_stride * ring_len));
+  }
+  w.U64 = L.U64;
+  w.Ulow = L.Ulow;
+  L.stride = (long long)(c.off - start);
+  c.off = start + (size_t)L.stride * (size_t)nrhs;
+  L.bytes = c.off;
+  return L;
+}
+
+template <class T>
+T* shift_ptr(T* p, long long off) {
+  return p ? reinterpret_cast<T*>(reinterpret_cast<char*>(p) + off) : p;
+}
+SpinorBuf shift_buf(SpinorBuf b, long long off) {
+  b.data = shift_ptr(static_cast<char*>(b.data), off);
+  b.scale = shift_ptr(b.scale, off);
+  return b;
+}
+
+// System k's region seen as a single-system workspace.
+CgWorkspace system_view(const LockstepWorkspace& L, int k) {
+  const long long off = (long long)k * L.stride;
+  CgWorkspace w = L.sys0;
+  w.st = shift_ptr(w.st, off);
+  w.partials = shift_ptr(w.partials, off);
+  w.hist = shift_ptr(w.hist, off);
+  w.b64 = shift_buf(w.b64, off);
+  w.x64 = shift_buf(w.x64, off);
+  w.t64 = shift_buf(w.t64, off);
+  w.rh = shift_buf(w.rh, off);
+  w.th = shift_buf(w.th, off);
+  w.alpha_hist = shift_ptr(w.alpha_hist, off);
+  w.ring.data = shift_ptr(w.ring.data, off);
+  w.ring.scale = shift_ptr(w.ring.scale, off);
+  return w;
+}
+
+// The lockstep kernels exist for 16- and 8-bit storage with reliable updates
+// on the tiled site order.
+bool lockstep_possible(const Geom& g, const wd_cg_params* p) {
+  return g.tiled && narrow_prec(p->inner_prec) && p->scheme == WD_RELIABLE_UPDATE;
+}
+bool use_lockstep(const Geom& g, const wd_cg_params* p) {
+  return p->batch_schedule == WD_BATCH_LOCKSTEP || (p->batch_schedule == WD_BATCH_AUTO && lockstep_possible(g, p));
+}
+
 // Host mirrors of the device state, pinned, one pair per device.
 struct HostMirror {
   SolverState* buf[2] = {nullptr, nullptr};
@@ -267,13 +360,18 @@ int validate_params(const wd_cg_params* p) {
   if (!(p->inner_tol >= 0.0 && p->inner_tol < 1.0)) return fail(WD_ERR_INVALID, "inner_tol = %g not in [0, 1)", p->inner_tol);
   if (p->ring_len != 0 && (p->ring_len < 8 || p->ring_len > 256))
     return fail(WD_ERR_INVALID, "ring_len = %d must be 0 or in [8, 256]", p->ring_len);
+  if (p->batch_schedule != WD_BATCH_AUTO && p->batch_schedule != WD_BATCH_PERSISTENT &&
+      p->batch_schedule != WD_BATCH_LOCKSTEP)
+    return fail(WD_ERR_INVALID, "batch_schedule = %d unknown", p->batch_schedule);
   return WD_OK;
 }
 
 // The documented workspace size: for nrhs = 1 it covers both cg_solve and a
 // single-system cg_solve_batched.
 size_t required_bytes(const Geom& g, const wd_cg_params* p, int nrhs) {
-  const size_t batched = batched_workspace_bytes(g, nrhs, p->history_len, p->inner_prec);
+  size_t batched = batched_workspace_bytes(g, nrhs, p->history_len, p->inner_prec);
+  if (use_lockstep(g, p) && lockstep_possible(g, p))
+    batched = std::max(batched, layout_lockstep(nullptr, g, p->inner_prec, ring_length_batch(p, g, nrhs), nrhs).bytes);
   if (nrhs == 1)
     return std::max(layout_cg(nullptr, g, p->inner_prec, p->history_len, ring_length(p, g)).bytes, batched);
   return batched;
@@ -495,9 +593,9 @@ int copy_history(const double* hist, const wd_cg_params* p, hipStream_t s, int i
 // Shared set-up: pack U and b, form b', zero or pack x, and the initial
 // residual r = b' - D^+ D x written to `rout` in its precision.
 int cg_setup(const Geom& g, double mass, const void* U, const void* b, void* x, const wd_cg_params* p,
-             const CgWorkspace& w, int interval, double delta, SpinorBuf rout, hipStream_t s) {
+             const CgWorkspace& w, int interval, double delta, SpinorBuf rout, hipStream_t s, bool pack_u = true) {
   launch_init_state(w.st, p->tol, interval, delta, w.hist, p->history_len, s);
-  launch_pack_gauge(g, U, P_F64, w.U64, s);
+  if (pack_u) launch_pack_gauge(g, U, P_F64, w.U64, s);
   const int c64 = p->io_dtype == WD_C64;
   if (p->rhs_mode == WD_RHS_SOURCE) {
     launch_pack_spinor(g, b, c64, w.t64, s);
@@ -701,6 +799,168 @@ int cg_mixed(const Geom& g, double mass, const void* U, const void* b, void* x, 
   return fill_result(res, st, code, secs, iter_rel);
 }
 
+// ---- lockstep batched solve: cg_mixed's schedule with every launch of the
+// inner loop and of the reliable-update slots covering all systems (Rhs).
+// Each system keeps its own state, so a converged system's workgroups exit
+// at its closed gates while the others continue.
+
+struct BatchMirror {
+  SolverState* buf[2] = {nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+};
+BatchMirror g_batch_mirror[64];
+
+int get_batch_mirror(BatchMirror** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(WD_ERR_HIP, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_mirror_mu);
+  BatchMirror& m = g_batch_mirror[dev];
+  if (!m.buf[0]) {
+    for (int i = 0; i < 2; ++i) {
+      HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&m.buf[i]), sizeof(SolverState) * kMaxBatch,
+                            hipHostMallocDefault));
+      HIP_TRY(hipEventCreateWithFlags(&m.ev[i], hipEventDisableTiming));
+    }
+  }
+  *out = &m;
+  return WD_OK;
+}
+
+int cg_mixed_lockstep(const Geom& g, double mass, const void* U, int nrhs, const void* B, void* X,
+                      const wd_cg_params* p, wd_cg_result* res, void* ws, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const int P = p->inner_prec;
+  const int interval = reliable_interval_of(p);
+  const LockstepWorkspace L = layout_lockstep(ws, g, P, ring_length_batch(p, g, nrhs), nrhs);
+  const CgWorkspace& w = L.sys0;
+  const Rhs rb{nrhs, L.stride};
+  double delta = (P == WD_BF16 || P == WD_I8) ? 0.1 : (P == WD_F16) ? 1e-2 : 1e-4;
+  if (p->inner_tol > 0.0) delta = p->inner_tol;
+  const int c64 = p->io_dtype == WD_C64;
+  const size_t io_stride = (size_t)g.V * 12 * (c64 ? 8 : 16);
+  wd_cg_params q = *p;   // per-system set-up, without a residual history
+  q.history = nullptr;
+  q.history_len = 0;
+  int rc;
+  BatchMirror* m;
+  if ((rc = get_batch_mirror(&m))) return rc;
+
+  // shared links: FP64 for the reliable updates; low precision, two rows when SU(3)
+  launch_pack_gauge(g, U, P_F64, L.U64, s);
+  launch_init_state(w.st, p->tol, interval, delta, w.hist, 0, s);
+  launch_su3_check(g, U, w.st, w.partials, s);
+  HIP_TRY(hipMemcpyAsync(m->buf[0], w.st, sizeof(SolverState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const int rows2 = m->buf[0]->su3_dev <= 1e-9;
+  if (rows2) launch_pack_gauge_rows2(g, U, P, L.Ulow, s);
+  else launch_pack_gauge(g, U, P, L.Ulow, s);
+  for (int k = 0; k < nrhs; ++k) {
+    const CgWorkspace wk = system_view(L, k);
+    const void* bk = static_cast<const char*>(B) + k * io_stride;
+    void* xk = static_cast<char*>(X) + k * io_stride;
+    if ((rc = cg_setup(g, mass, U, bk, xk, &q, wk, interval, delta, wk.rh, s, false))) return rc;
+    launch_convert(g, wk.rh, wk.ring.at(0), G_ALWAYS, wk.st, s);
+    launch_set_ring(wk.st, wk.alpha_hist, wk.ring.len - (kSlotEvery - 1), wk.ring.len, s);
+  }
+  HIP_TRY(hipGetLastError());
+
+  SolverState st[kMaxBatch];
+  for (int k = 0; k < nrhs; ++k) {
+    st[k] = SolverState{};
+    st[k].stop2 = 1;
+  }
+  int slot = 0, pending = 0, enqueued = 0;
+  auto post = [&]() -> int {
+    launch_gather_states(w.st, rb, L.states, s);
+    HIP_TRY(hipMemcpyAsync(m->buf[slot], L.states, sizeof(SolverState) * nrhs, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(m->ev[slot], s));
+    slot ^= 1;
+    ++pending;
+    return WD_OK;
+  };
+  auto wait = [&]() -> int {   // the oldest posted copy
+    const int j = pending == 2 ? slot : slot ^ 1;
+    HIP_TRY(hipEventSynchronize(m->ev[j]));
+    for (int k = 0; k < nrhs; ++k) st[k] = m->buf[j][k];
+    --pending;
+    return WD_OK;
+  };
+  for (;;) {
+    while (pending < 2) {
+      // enough iterations for the slowest system still running
+      int n = 0;
+      for (int k = 0; k < nrhs; ++k)
+        if (st[k].status == 0) n = std::max(n, next_chunk(st[k], enqueued, p->max_iter));
+      if (n <= 0) break;
+      for (int i = 0; i < n; ++i) {
+        launch_wilson_packed(g, P, w.Ulow, w.rh, w.th, mass, 0, G_ITER, F_ALPHA_RING, w.st, w.partials, s, nullptr,
+                             rows2, &w.ring, rb);
+        launch_r_update(g, P, w.Ulow, w.th, w.rh, mass, w.st, w.partials, s, nullptr, rows2, rb);
+        if ((enqueued + i + 1) % kSlotEvery == 0) {
+          launch_accumulate_ring(g, w.x64, w.ring, G_FLUSH, w.st, s, rb);
+          launch_ring_reset(w.st, s, rb);
+          launch_accumulate_ring(g, w.x64, w.ring, G_RELIABLE, w.st, s, rb);
+          launch_wilson_packed(g, P_F64, w.U64, w.x64, w.t64, mass, 0, G_RELIABLE, F_NONE, w.st, w.partials, s,
+                               nullptr, 0, nullptr, rb);
+          launch_residual(g, w.U64, w.t64, w.b64, w.rh, mass, G_RELIABLE, F_RELIABLE, w.st, w.partials, s, rb);
+        }
+        launch_p_update_ring(g, w.rh, w.ring, w.st, s, nullptr, rb);
+      }
+      enqueued += n;
+      HIP_TRY(hipGetLastError());
+      if ((rc = post())) return rc;
+    }
+    if (pending == 0) break;
+    if ((rc = wait())) return rc;
+    bool more = false;   // a system still running that more iterations can serve
+    for (int k = 0; k < nrhs; ++k)
+      if (st[k].status == 0 && !(st[k].inner_done && enqueued >= p->max_iter)) more = true;
+    if (!more) break;
+  }
+  while (pending > 0)
+    if ((rc = wait())) return rc;
+  double iter_rel[kMaxBatch];
+  for (int k = 0; k < nrhs; ++k) {
+    iter_rel[k] = std::sqrt(st[k].rho / (st[k].bnorm2 > 0 ? st[k].bnorm2 : 1.0));
+    if (st[k].status == 1) continue;
+    // max_iter reached (or an error): fold the pending directions, measure the true residual
+    const CgWorkspace wk = system_view(L, k);
+    launch_accumulate_ring(g, wk.x64, wk.ring, G_FINAL, wk.st, s);
+    launch_wilson_packed(g, P_F64, wk.U64, wk.x64, wk.t64, mass, 0, G_FINAL, F_NONE, wk.st, wk.partials, s);
+    launch_residual(g, wk.U64, wk.t64, wk.b64, wk.rh, mass, G_FINAL, F_TRUE, wk.st, wk.partials, s);
+  }
+  for (int k = 0; k < nrhs; ++k)
+    launch_unpack_spinor(g, system_view(L, k).x64, static_cast<char*>(X) + k * io_stride, c64, s);
+  HIP_TRY(hipGetLastError());
+  if ((rc = post())) return rc;
+  if ((rc = wait())) return rc;
+  HIP_TRY(hipStreamSynchronize(s));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int code = WD_OK;
+  for (int k = 0; k < nrhs; ++k) {
+    const SolverState& sk = st[k];
+    int ck;
+    if (sk.status == -4) ck = WD_ERR_NAN;
+    else if (sk.status == -3) ck = WD_ERR_BREAKDOWN;
+    else if (sk.status < 0) ck = WD_ERR_HIP;
+    else if (sk.rho_true <= sk.stop2) ck = WD_OK;
+    else ck = WD_NOT_CONVERGED;
+    if (ck < 0 && (code >= 0 || ck < code)) code = ck;
+    else if (ck == WD_NOT_CONVERGED && code == WD_OK) code = WD_NOT_CONVERGED;
+    if (res) {
+      fill_result(&res[k], sk, ck, secs, iter_rel[k]);
+      res[k].two_row_links = rows2;
+      for (int j = 0; j < 3; ++j) res[k].kernel_seconds[j] = 0.0;
+    }
+  }
+  if (code == WD_NOT_CONVERGED)
+    return fail(code, "at least one system did not converge in %d iterations", p->max_iter);
+  if (code == WD_ERR_HIP) return fail(code, "internal: search-direction ring overflow");
+  if (code < 0) return fail(code, "a system ended with status %d (NaN/Inf or breakdown)", code);
+  return WD_OK;
+}
+
 // ---- the gauge-covariant Laplacian: the same state, gates, reductions and
 // host loop as cg_plain, with the colour-vector stencil and updates.
 
@@ -891,6 +1151,11 @@ extern "C" int cg_solve_batched(const wd_lattice* lat, double mass, const void* 
   const size_t need = required_bytes(g, params, nrhs);
   if (!workspace || ws_bytes < need)
     return fail(WD_ERR_WORKSPACE, "workspace of %zu bytes given, %zu needed", workspace ? ws_bytes : 0, need);
+  if (params->batch_schedule == WD_BATCH_LOCKSTEP && !lockstep_possible(g, params))
+    return fail(WD_ERR_INVALID, "lockstep batching needs BF16, FP16 or int8 inner storage, reliable updates "
+                                "and lattice extents that are multiples of 4");
+  if (use_lockstep(g, params))
+    return cg_mixed_lockstep(g, mass, U, nrhs, B, X, params, results, workspace, as_stream(stream));
   char err[512] = {0};
   rc = batched_solve(g, mass, U, nrhs, B, X, params, results, workspace, as_stream(stream), err, sizeof(err));
   if (rc != WD_OK) return fail(rc, "%s", err);

@@ -201,6 +201,12 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   if (b < (per << 3)) return (b & 7) * per + (b >> 3);
   return b;
 }
+// The workgroup index b with xcd_tile(b, nb) == T.
+__device__ __forceinline__ int xcd_tile_inv(int T, int nb) {
+  const int per = nb >> 3;
+  if (T < (per << 3)) return (T % per) * 8 + T / per;
+  return T;
+}
 
 // ----------------------------------------------------------- conversions
 

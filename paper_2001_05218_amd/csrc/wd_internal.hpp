@@ -99,6 +99,15 @@ struct RingBuf {
   }
 };
 
+// Several systems in one launch (the lockstep batched solver): the state,
+// partials, vectors and ring of system k lie `stride` bytes after those of
+// system k - 1; the gauge fields are shared and not offset. The default is a
+// single system.
+struct Rhs {
+  int n = 1;
+  long long stride = 0;
+};
+
 // ---- launchers (wd_kernels.hip). All asynchronous on `stream`.
 // Reset the state: stop2 = tol^2 (scaled by ||b'||^2 at F_BNORM), interval 0 = plain CG.
 void launch_init_state(SolverState* st, double tol, int interval, double delta, double* hist, int hist_len,
@@ -120,7 +129,8 @@ void launch_wilson_canonical(const Geom& g, const void* U, const void* in, void*
 // With `ring`, the input is ring slot st->npend instead of `in` (mixed solver).
 void launch_wilson_packed(const Geom& g, int prec, const void* U, SpinorBuf in, SpinorBuf out, double mass,
                           int dagger, int gate, int fin, SolverState* st, double* partials, hipStream_t s,
-                          const EventPair* ev = nullptr, int rows2 = 0, const RingBuf* ring = nullptr);
+                          const EventPair* ev = nullptr, int rows2 = 0, const RingBuf* ring = nullptr,
+                          Rhs rb = {});
 // Two-row (12-real) 16-bit gauge copy (BF16 or FP16), tiled lattices; the
 // tiled 16-bit kernels rebuild row 2 from unitarity (rows2 = 1).
 void launch_pack_gauge_rows2(const Geom& g, const void* U_c128, int prec, void* out, hipStream_t s);
@@ -133,7 +143,7 @@ void launch_cg_update(const Geom& g, int prec, const void* U, SpinorBuf t, Spino
                       int rows2 = 0);
 // out = low(b - D^+ t) with FP64 arithmetic on FP64 fields; ||b - D^+ t||^2 -> fin.
 void launch_residual(const Geom& g, const void* U64, SpinorBuf t64, SpinorBuf b64, SpinorBuf out, double mass,
-                     int gate, int fin, SolverState* st, double* partials, hipStream_t s);
+                     int gate, int fin, SolverState* st, double* partials, hipStream_t s, Rhs rb = {});
 // p = r + beta p
 void launch_p_update(const Geom& g, SpinorBuf r, SpinorBuf p, SolverState* st, hipStream_t s,
                      const EventPair* ev = nullptr);
@@ -141,15 +151,18 @@ void launch_p_update(const Geom& g, SpinorBuf r, SpinorBuf p, SolverState* st, h
 //   t = D ring[npend] (+ ||t||^2 -> F_ALPHA_RING) is launch_wilson_packed with `ring`;
 //   q = D^+ t (never stored); r -= alpha q; ||r||^2 -> F_BETA.
 void launch_r_update(const Geom& g, int prec, const void* U, SpinorBuf t, SpinorBuf r, double mass, SolverState* st,
-                     double* partials, hipStream_t s, const EventPair* ev = nullptr, int rows2 = 0);
+                     double* partials, hipStream_t s, const EventPair* ev = nullptr, int rows2 = 0,
+                     Rhs rb = {});
 //   ring[npend] = r + beta ring[pcur] (in place when the two slots coincide).
 void launch_p_update_ring(const Geom& g, SpinorBuf r, const RingBuf& ring, SolverState* st, hipStream_t s,
-                          const EventPair* ev = nullptr);
+                          const EventPair* ev = nullptr, Rhs rb = {});
 //   x(FP64) += sum_{j < npend} alpha_hist[j] ring[j], accumulated in FP64.
 void launch_accumulate_ring(const Geom& g, SpinorBuf x64, const RingBuf& ring, int gate, SolverState* st,
-                            hipStream_t s);
+                            hipStream_t s, Rhs rb = {});
 //   npend = 0 when G_FLUSH is open (after launch_accumulate_ring with G_FLUSH).
-void launch_ring_reset(SolverState* st, hipStream_t s);
+void launch_ring_reset(SolverState* st, hipStream_t s, Rhs rb = {});
+// dst[k] = the state of system k (a contiguous copy for the host to read).
+void launch_gather_states(const SolverState* st, Rhs rb, SolverState* dst, hipStream_t s);
 //   alpha_hist, flush_at and ring_len of the state.
 void launch_set_ring(SolverState* st, double* alpha_hist, int flush_at, int ring_len, hipStream_t s);
 // x(FP64) += xhat; xhat = 0

@@ -100,7 +100,11 @@ constexpr int kFinBlock = 1024;
 // the same gate as the kernel that wrote the partials (which did not change
 // the state), so both are skipped or run together.
 __global__ __launch_bounds__(kFinBlock) void k_finalize(const double* __restrict__ partials, int n, SolverState* st,
-                                                        int fin, int gate) {
+                                                        int fin, int gate, Rhs rb) {
+  // one workgroup per system
+  const long long off = (long long)blockIdx.x * rb.stride;
+  partials = rhs_shift(partials, off);
+  st = rhs_shift(st, off);
   if (!gate_open(st, gate)) return;
   __shared__ double wsum[kFinBlock / 64];
   const bool use_max = (fin == F_SU3MAX);
@@ -132,11 +136,20 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(const double* __restrict
 }
 
 void launch_finalize_n(int n, double* partials, SolverState* st, int fin, int gate, hipStream_t s) {
-  k_finalize<<<1, kFinBlock, 0, s>>>(partials, n, st, fin, gate);
+  k_finalize<<<1, kFinBlock, 0, s>>>(partials, n, st, fin, gate, Rhs{});
 }
 
-static void launch_finalize(const Geom& g, double* partials, SolverState* st, int fin, int gate, hipStream_t s) {
-  launch_finalize_n(g.nblocks, partials, st, fin, gate, s);
+static void launch_finalize(const Geom& g, double* partials, SolverState* st, int fin, int gate, hipStream_t s,
+                            Rhs rb = {}) {
+  k_finalize<<<rb.n, kFinBlock, 0, s>>>(partials, g.nblocks, st, fin, gate, rb);
+}
+
+// Where a tile kernel stores tile T's partial: the slot that the workgroup of
+// tile T has in a single-system launch, so that a system's partials are
+// summed in the same order whether it is solved alone or in a lockstep batch
+// (identical iterates either way).
+__device__ __forceinline__ int partial_slot(int T, const Rhs& rb) {
+  return rb.n == 1 ? (int)blockIdx.x : xcd_tile_inv(T, (int)gridDim.x / rb.n);
 }
 
 // ------------------------------------------------------- spinor dispatch
@@ -331,14 +344,23 @@ __device__ __forceinline__ void stencil_at(const Geom& g, const void* U, const S
 template <int P, bool DAG, bool TILE>
 __global__ __launch_bounds__(kBlock) void k_wilson_packed(Geom g, const void* U, SpinorBuf in, SpinorBuf out,
                                                           double diag, int gate, int fin, SolverState* st,
-                                                          double* partials, RingBuf ring) {
+                                                          double* partials, RingBuf ring, Rhs rb) {
+  int k;
+  const int T = rhs_split(xcd_tile(blockIdx.x, gridDim.x), rb, k);
+  if (k) {
+    const long long off = k * rb.stride;
+    st = rhs_shift(st, off);
+    partials = rhs_shift(partials, off);
+    in = rhs_shift(in, off);
+    out = rhs_shift(out, off);
+    ring = rhs_shift(ring, off);
+  }
   if (!gate_open(st, gate)) return;
   if (ring.data) {
     if (st->npend >= ring.len) return;   // never with the host's fold cadence
     in = ring.at(st->npend);
   }
   using R = typename PackedSpinor<P>::Real;
-  const int T = xcd_tile(blockIdx.x, gridDim.x);
   const int s = T * kBlock + threadIdx.x;
   double n2 = 0.0;
   if (TILE || s < g.V) {
@@ -350,7 +372,7 @@ __global__ __launch_bounds__(kBlock) void k_wilson_packed(Geom g, const void* U,
       for (int i = 0; i < 24; ++i) n2 += (double)o[i] * (double)o[i];
     }
   }
-  if (fin != F_NONE) store_partial(n2, partials);
+  if (fin != F_NONE) store_partial(n2, partials, partial_slot(T, rb));
 }
 
 // LDS-staged stencil (16-bit storage, tiled order): one workgroup per 4^4 tile.
@@ -361,14 +383,23 @@ __global__ __launch_bounds__(kBlock) void k_wilson_packed(Geom g, const void* U,
 template <int P, bool C12, bool DAG>
 __global__ __launch_bounds__(kBlock) WD_TILED_OCCUPANCY void k_wilson_tiled(Geom g, const void* U, SpinorBuf in, SpinorBuf out,
                                                          double diag, int gate, int fin, SolverState* st,
-                                                         double* partials, RingBuf ring) {
+                                                         double* partials, RingBuf ring, Rhs rb) {
+  int k;
+  const int T = rhs_split(xcd_tile(blockIdx.x, gridDim.x), rb, k);
+  if (k) {
+    const long long off = k * rb.stride;
+    st = rhs_shift(st, off);
+    partials = rhs_shift(partials, off);
+    in = rhs_shift(in, off);
+    out = rhs_shift(out, off);
+    ring = rhs_shift(ring, off);
+  }
   if (!gate_open(st, gate)) return;
   if (ring.data) {
     if (st->npend >= ring.len) return;   // never with the host's fold cadence
     in = ring.at(st->npend);
   }
   __shared__ TileLds<P> lds;
-  const int T = xcd_tile(blockIdx.x, gridDim.x);
   uint32_t lk[8][9];
   tile_stage<P, C12>(g, T, U, in, lds, lk);
   __syncthreads();
@@ -380,7 +411,7 @@ __global__ __launch_bounds__(kBlock) WD_TILED_OCCUPANCY void k_wilson_tiled(Geom
     double n2 = 0.0;
 #pragma unroll
     for (int i = 0; i < 24; ++i) n2 += (double)o[i] * (double)o[i];
-    store_partial(n2, partials);
+    store_partial(n2, partials, partial_slot(T, rb));
   }
 }
 
@@ -389,10 +420,18 @@ __global__ __launch_bounds__(kBlock) WD_TILED_OCCUPANCY void k_wilson_tiled(Geom
 // solution update is deferred (the search directions wait in a ring).
 template <int P, bool C12>
 __global__ __launch_bounds__(kBlock) WD_TILED_OCCUPANCY void k_cg_update_tiled(Geom g, const void* U, SpinorBuf t, SpinorBuf r,
-                                                            double diag, SolverState* st, double* partials) {
+                                                            double diag, SolverState* st, double* partials, Rhs rb) {
+  int k;
+  const int T = rhs_split(xcd_tile(blockIdx.x, gridDim.x), rb, k);
+  if (k) {
+    const long long off = k * rb.stride;
+    st = rhs_shift(st, off);
+    partials = rhs_shift(partials, off);
+    t = rhs_shift(t, off);
+    r = rhs_shift(r, off);
+  }
   if (!gate_open(st, G_ITER)) return;
   __shared__ TileLds<P> lds;
-  const int T = xcd_tile(blockIdx.x, gridDim.x);
   uint32_t lk[8][9];
   tile_stage<P, C12>(g, T, U, t, lds, lk);
   __syncthreads();
@@ -427,7 +466,7 @@ __global__ __launch_bounds__(kBlock) WD_TILED_OCCUPANCY void k_cg_update_tiled(G
 #pragma unroll
     for (int i = 0; i < 24; ++i) n2 += (double)rv[i] * (double)rv[i];
   }
-  store_partial(n2, partials);
+  store_partial(n2, partials, partial_slot(T, rb));
 }
 
 // q = D^+ t at site s; r -= alpha q; x += alpha p; reduce ||r||^2 (of the stored r).
@@ -479,9 +518,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8))) 
 template <int PO, bool TILE>
 __global__ __launch_bounds__(kBlock) void k_residual(Geom g, const void* U64, SpinorBuf t64, SpinorBuf b64,
                                                      SpinorBuf out, double diag, int gate, int fin, SolverState* st,
-                                                     double* partials) {
+                                                     double* partials, Rhs rb) {
+  int k;
+  const int T = rhs_split(xcd_tile(blockIdx.x, gridDim.x), rb, k);
+  if (k) {
+    const long long off = k * rb.stride;
+    st = rhs_shift(st, off);
+    partials = rhs_shift(partials, off);
+    t64 = rhs_shift(t64, off);
+    b64 = rhs_shift(b64, off);
+    out = rhs_shift(out, off);
+  }
   if (!gate_open(st, gate)) return;
-  const int T = xcd_tile(blockIdx.x, gridDim.x);
   const int s = T * kBlock + threadIdx.x;
   double n2 = 0.0;
   if (TILE || s < g.V) {
@@ -497,7 +545,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(Geom g, const void* U64, Sp
     }
     spinor_of<PO>(out).store(s, o);
   }
-  store_partial(n2, partials);
+  store_partial(n2, partials, partial_slot(T, rb));
 }
 
 template <int P>
@@ -536,10 +584,19 @@ __global__ __launch_bounds__(kBlock) void k_accumulate(Geom g, SpinorBuf x64, Sp
 
 // Mixed solver, deferred x update: ring[npend] = r + beta ring[pcur].
 template <int P>
-__global__ __launch_bounds__(kBlock) void k_p_update_ring(Geom g, SpinorBuf r, RingBuf ring, const SolverState* st) {
+__global__ __launch_bounds__(kBlock) void k_p_update_ring(Geom g, SpinorBuf r, RingBuf ring, const SolverState* st,
+                                                          Rhs rb) {
+  int k;
+  const int b = rhs_split(blockIdx.x, rb, k);
+  if (k) {
+    const long long off = k * rb.stride;
+    st = rhs_shift(st, off);
+    r = rhs_shift(r, off);
+    ring = rhs_shift(ring, off);
+  }
   if (!gate_open(st, G_ITER)) return;
   using R = typename PackedSpinor<P>::Real;
-  const int s = blockIdx.x * kBlock + threadIdx.x;
+  const int s = b * kBlock + threadIdx.x;
   if (s >= g.V || st->npend >= ring.len) return;   // the latter never with the host's fold cadence
   const R beta = (R)st->beta;
   R rv[24], pv[24];
@@ -553,9 +610,17 @@ __global__ __launch_bounds__(kBlock) void k_p_update_ring(Geom g, SpinorBuf r, R
 // x(FP64) += sum_{j < npend} alpha_j p_j over the ring, in FP64 arithmetic.
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_accumulate_ring(Geom g, SpinorBuf x64, RingBuf ring, int gate,
-                                                            const SolverState* st) {
+                                                            const SolverState* st, Rhs rb) {
+  int k;
+  const int b = rhs_split(blockIdx.x, rb, k);
+  if (k) {
+    const long long off = k * rb.stride;
+    st = rhs_shift(st, off);
+    x64 = rhs_shift(x64, off);
+    ring = rhs_shift(ring, off);
+  }
   if (!gate_open(st, gate)) return;
-  const int s = blockIdx.x * kBlock + threadIdx.x;
+  const int s = b * kBlock + threadIdx.x;
   if (s >= g.V) return;
   const int n = st->npend;
   if (n == 0) return;
@@ -571,10 +636,17 @@ __global__ __launch_bounds__(kBlock) void k_accumulate_ring(Geom g, SpinorBuf x6
   spinor_of<P_F64>(x64).store(s, xv);
 }
 
-__global__ void k_ring_reset(SolverState* st) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ void k_ring_reset(SolverState* st, Rhs rb) {
+  if (threadIdx.x != 0) return;
+  st = rhs_shift(st, (long long)blockIdx.x * rb.stride);   // one workgroup per system
   if (!gate_open(st, G_FLUSH)) return;
   st->npend = 0;
+}
+
+__global__ void k_gather_states(const SolverState* st, Rhs rb, SolverState* dst) {
+  const int k = blockIdx.x;
+  if (threadIdx.x != 0 || k >= rb.n) return;
+  dst[k] = *rhs_shift(st, (long long)k * rb.stride);
 }
 
 __global__ void k_set_ring(SolverState* st, double* alpha_hist, int flush_at, int ring_len) {
@@ -809,54 +881,59 @@ void launch_wilson_canonical(const Geom& g, const void* U, const void* in, void*
 // this dispatch (hipExtLaunchKernel), so they time the kernel alone, as the
 // profiler's kernel trace does.
 template <typename... KArgs, typename... Args>
-static void launch(void (*kernel)(KArgs...), const Geom& g, hipStream_t s, const EventPair* ev, Args... args) {
+static void launch_n(void (*kernel)(KArgs...), const Geom& g, int n, hipStream_t s, const EventPair* ev,
+                     Args... args) {
+  const dim3 grid(g.nblocks * n);
   if (ev)
-    hipExtLaunchKernelGGL(kernel, grid_of(g), dim3(kBlock), 0, s, ev->begin, ev->end, 0,
-                          static_cast<KArgs>(args)...);
+    hipExtLaunchKernelGGL(kernel, grid, dim3(kBlock), 0, s, ev->begin, ev->end, 0, static_cast<KArgs>(args)...);
   else
-    kernel<<<grid_of(g), kBlock, 0, s>>>(static_cast<KArgs>(args)...);
+    kernel<<<grid, kBlock, 0, s>>>(static_cast<KArgs>(args)...);
+}
+template <typename... KArgs, typename... Args>
+static void launch(void (*kernel)(KArgs...), const Geom& g, hipStream_t s, const EventPair* ev, Args... args) {
+  launch_n(kernel, g, 1, s, ev, args...);
 }
 
 template <int P>
 static void wilson_packed_p(const Geom& g, const void* U, SpinorBuf in, SpinorBuf out, double mass, int dagger,
                             int gate, int fin, SolverState* st, double* partials, hipStream_t s,
-                            const EventPair* ev, int rows2, RingBuf ring) {
+                            const EventPair* ev, int rows2, RingBuf ring, Rhs rb) {
   const double d = mass + 4.0;
   bool done = false;
   if constexpr (P == P_BF16 || P == P_F16 || P == P_I8) {
     if (g.tiled) {
-      if (rows2 && dagger) launch(k_wilson_tiled<P, true, true>, g, s, ev, g, U, in, out, d, gate, fin, st, partials, ring);
-      else if (rows2) launch(k_wilson_tiled<P, true, false>, g, s, ev, g, U, in, out, d, gate, fin, st, partials, ring);
-      else if (dagger) launch(k_wilson_tiled<P, false, true>, g, s, ev, g, U, in, out, d, gate, fin, st, partials, ring);
-      else launch(k_wilson_tiled<P, false, false>, g, s, ev, g, U, in, out, d, gate, fin, st, partials, ring);
+      if (rows2 && dagger) launch_n(k_wilson_tiled<P, true, true>, g, rb.n, s, ev, g, U, in, out, d, gate, fin, st, partials, ring, rb);
+      else if (rows2) launch_n(k_wilson_tiled<P, true, false>, g, rb.n, s, ev, g, U, in, out, d, gate, fin, st, partials, ring, rb);
+      else if (dagger) launch_n(k_wilson_tiled<P, false, true>, g, rb.n, s, ev, g, U, in, out, d, gate, fin, st, partials, ring, rb);
+      else launch_n(k_wilson_tiled<P, false, false>, g, rb.n, s, ev, g, U, in, out, d, gate, fin, st, partials, ring, rb);
       done = true;
     }
   }
   if constexpr (P == P_F64 || P == P_F32) {
     if (g.tiled) {
-      if (dagger) launch(k_wilson_packed<P, true, true>, g, s, ev, g, U, in, out, d, gate, fin, st, partials, ring);
-      else launch(k_wilson_packed<P, false, true>, g, s, ev, g, U, in, out, d, gate, fin, st, partials, ring);
+      if (dagger) launch_n(k_wilson_packed<P, true, true>, g, rb.n, s, ev, g, U, in, out, d, gate, fin, st, partials, ring, rb);
+      else launch_n(k_wilson_packed<P, false, true>, g, rb.n, s, ev, g, U, in, out, d, gate, fin, st, partials, ring, rb);
       done = true;
     }
   }
   if (!done) {
-    if (dagger) launch(k_wilson_packed<P, true, false>, g, s, ev, g, U, in, out, d, gate, fin, st, partials, ring);
-    else launch(k_wilson_packed<P, false, false>, g, s, ev, g, U, in, out, d, gate, fin, st, partials, ring);
+    if (dagger) launch_n(k_wilson_packed<P, true, false>, g, rb.n, s, ev, g, U, in, out, d, gate, fin, st, partials, ring, rb);
+    else launch_n(k_wilson_packed<P, false, false>, g, rb.n, s, ev, g, U, in, out, d, gate, fin, st, partials, ring, rb);
   }
-  if (fin != F_NONE) launch_finalize(g, partials, st, fin, gate, s);
+  if (fin != F_NONE) launch_finalize(g, partials, st, fin, gate, s, rb);
 }
 
 void launch_wilson_packed(const Geom& g, int prec, const void* U, SpinorBuf in, SpinorBuf out, double mass,
                           int dagger, int gate, int fin, SolverState* st, double* partials, hipStream_t s,
-                          const EventPair* ev, int rows2, const RingBuf* ring) {
+                          const EventPair* ev, int rows2, const RingBuf* ring, Rhs rb) {
   RingBuf rg{};
   if (ring) rg = *ring;
   switch (prec) {
-    case P_F64: wilson_packed_p<P_F64>(g, U, in, out, mass, dagger, gate, fin, st, partials, s, ev, 0, rg); break;
-    case P_F32: wilson_packed_p<P_F32>(g, U, in, out, mass, dagger, gate, fin, st, partials, s, ev, 0, rg); break;
-    case P_I8: wilson_packed_p<P_I8>(g, U, in, out, mass, dagger, gate, fin, st, partials, s, ev, rows2, rg); break;
-    case P_BF16: wilson_packed_p<P_BF16>(g, U, in, out, mass, dagger, gate, fin, st, partials, s, ev, rows2, rg); break;
-    default: wilson_packed_p<P_F16>(g, U, in, out, mass, dagger, gate, fin, st, partials, s, ev, rows2, rg); break;
+    case P_F64: wilson_packed_p<P_F64>(g, U, in, out, mass, dagger, gate, fin, st, partials, s, ev, 0, rg, rb); break;
+    case P_F32: wilson_packed_p<P_F32>(g, U, in, out, mass, dagger, gate, fin, st, partials, s, ev, 0, rg, rb); break;
+    case P_I8: wilson_packed_p<P_I8>(g, U, in, out, mass, dagger, gate, fin, st, partials, s, ev, rows2, rg, rb); break;
+    case P_BF16: wilson_packed_p<P_BF16>(g, U, in, out, mass, dagger, gate, fin, st, partials, s, ev, rows2, rg, rb); break;
+    default: wilson_packed_p<P_F16>(g, U, in, out, mass, dagger, gate, fin, st, partials, s, ev, rows2, rg, rb); break;
   }
 }
 
@@ -893,12 +970,12 @@ void launch_cg_update(const Geom& g, int prec, const void* U, SpinorBuf t, Spino
 // r update without the x and p terms (the mixed solver's deferred x update).
 template <int P>
 static void r_update_p(const Geom& g, const void* U, SpinorBuf t, SpinorBuf r, double diag, SolverState* st,
-                       double* partials, hipStream_t s, const EventPair* ev, int rows2) {
+                       double* partials, hipStream_t s, const EventPair* ev, int rows2, Rhs rb) {
   const SpinorBuf none{nullptr, nullptr, P};
   if constexpr (P == P_BF16 || P == P_F16 || P == P_I8) {
     if (g.tiled) {
-      if (rows2) launch(k_cg_update_tiled<P, true>, g, s, ev, g, U, t, r, diag, st, partials);
-      else launch(k_cg_update_tiled<P, false>, g, s, ev, g, U, t, r, diag, st, partials);
+      if (rows2) launch_n(k_cg_update_tiled<P, true>, g, rb.n, s, ev, g, U, t, r, diag, st, partials, rb);
+      else launch_n(k_cg_update_tiled<P, false>, g, rb.n, s, ev, g, U, t, r, diag, st, partials, rb);
       return;
     }
     launch(k_cg_update<P, P_F32, false, false>, g, s, ev, g, U, t, r, none, none, diag, st, partials);
@@ -909,69 +986,73 @@ static void r_update_p(const Geom& g, const void* U, SpinorBuf t, SpinorBuf r, d
 }
 
 void launch_r_update(const Geom& g, int prec, const void* U, SpinorBuf t, SpinorBuf r, double mass, SolverState* st,
-                     double* partials, hipStream_t s, const EventPair* ev, int rows2) {
+                     double* partials, hipStream_t s, const EventPair* ev, int rows2, Rhs rb) {
   const double diag = mass + 4.0;
   switch (prec) {
-    case P_F64: r_update_p<P_F64>(g, U, t, r, diag, st, partials, s, ev, 0); break;
-    case P_F32: r_update_p<P_F32>(g, U, t, r, diag, st, partials, s, ev, 0); break;
-    case P_I8: r_update_p<P_I8>(g, U, t, r, diag, st, partials, s, ev, rows2); break;
-    case P_BF16: r_update_p<P_BF16>(g, U, t, r, diag, st, partials, s, ev, rows2); break;
-    default: r_update_p<P_F16>(g, U, t, r, diag, st, partials, s, ev, rows2); break;
+    case P_F64: r_update_p<P_F64>(g, U, t, r, diag, st, partials, s, ev, 0, rb); break;
+    case P_F32: r_update_p<P_F32>(g, U, t, r, diag, st, partials, s, ev, 0, rb); break;
+    case P_I8: r_update_p<P_I8>(g, U, t, r, diag, st, partials, s, ev, rows2, rb); break;
+    case P_BF16: r_update_p<P_BF16>(g, U, t, r, diag, st, partials, s, ev, rows2, rb); break;
+    default: r_update_p<P_F16>(g, U, t, r, diag, st, partials, s, ev, rows2, rb); break;
   }
-  launch_finalize(g, partials, st, F_BETA, G_ITER, s);
+  launch_finalize(g, partials, st, F_BETA, G_ITER, s, rb);
 }
 
 void launch_p_update_ring(const Geom& g, SpinorBuf r, const RingBuf& ring, SolverState* st, hipStream_t s,
-                          const EventPair* ev) {
+                          const EventPair* ev, Rhs rb) {
   const SolverState* cst = st;
   switch (ring.prec) {
-    case P_F64: launch(k_p_update_ring<P_F64>, g, s, ev, g, r, ring, cst); break;
-    case P_F32: launch(k_p_update_ring<P_F32>, g, s, ev, g, r, ring, cst); break;
-    case P_I8: launch(k_p_update_ring<P_I8>, g, s, ev, g, r, ring, cst); break;
-    case P_BF16: launch(k_p_update_ring<P_BF16>, g, s, ev, g, r, ring, cst); break;
-    default: launch(k_p_update_ring<P_F16>, g, s, ev, g, r, ring, cst); break;
+    case P_F64: launch_n(k_p_update_ring<P_F64>, g, rb.n, s, ev, g, r, ring, cst, rb); break;
+    case P_F32: launch_n(k_p_update_ring<P_F32>, g, rb.n, s, ev, g, r, ring, cst, rb); break;
+    case P_I8: launch_n(k_p_update_ring<P_I8>, g, rb.n, s, ev, g, r, ring, cst, rb); break;
+    case P_BF16: launch_n(k_p_update_ring<P_BF16>, g, rb.n, s, ev, g, r, ring, cst, rb); break;
+    default: launch_n(k_p_update_ring<P_F16>, g, rb.n, s, ev, g, r, ring, cst, rb); break;
   }
 }
 
 void launch_accumulate_ring(const Geom& g, SpinorBuf x64, const RingBuf& ring, int gate, SolverState* st,
-                            hipStream_t s) {
+                            hipStream_t s, Rhs rb) {
   const SolverState* cst = st;
   switch (ring.prec) {
-    case P_F64: launch(k_accumulate_ring<P_F64>, g, s, nullptr, g, x64, ring, gate, cst); break;
-    case P_F32: launch(k_accumulate_ring<P_F32>, g, s, nullptr, g, x64, ring, gate, cst); break;
-    case P_I8: launch(k_accumulate_ring<P_I8>, g, s, nullptr, g, x64, ring, gate, cst); break;
-    case P_BF16: launch(k_accumulate_ring<P_BF16>, g, s, nullptr, g, x64, ring, gate, cst); break;
-    default: launch(k_accumulate_ring<P_F16>, g, s, nullptr, g, x64, ring, gate, cst); break;
+    case P_F64: launch_n(k_accumulate_ring<P_F64>, g, rb.n, s, nullptr, g, x64, ring, gate, cst, rb); break;
+    case P_F32: launch_n(k_accumulate_ring<P_F32>, g, rb.n, s, nullptr, g, x64, ring, gate, cst, rb); break;
+    case P_I8: launch_n(k_accumulate_ring<P_I8>, g, rb.n, s, nullptr, g, x64, ring, gate, cst, rb); break;
+    case P_BF16: launch_n(k_accumulate_ring<P_BF16>, g, rb.n, s, nullptr, g, x64, ring, gate, cst, rb); break;
+    default: launch_n(k_accumulate_ring<P_F16>, g, rb.n, s, nullptr, g, x64, ring, gate, cst, rb); break;
   }
 }
 
-void launch_ring_reset(SolverState* st, hipStream_t s) { k_ring_reset<<<1, 64, 0, s>>>(st); }
+void launch_ring_reset(SolverState* st, hipStream_t s, Rhs rb) { k_ring_reset<<<rb.n, 64, 0, s>>>(st, rb); }
+
+void launch_gather_states(const SolverState* st, Rhs rb, SolverState* dst, hipStream_t s) {
+  k_gather_states<<<rb.n, 64, 0, s>>>(st, rb, dst);
+}
 
 void launch_set_ring(SolverState* st, double* alpha_hist, int flush_at, int ring_len, hipStream_t s) {
   k_set_ring<<<1, 64, 0, s>>>(st, alpha_hist, flush_at, ring_len);
 }
 
 void launch_residual(const Geom& g, const void* U64, SpinorBuf t64, SpinorBuf b64, SpinorBuf out, double mass,
-                     int gate, int fin, SolverState* st, double* partials, hipStream_t s) {
+                     int gate, int fin, SolverState* st, double* partials, hipStream_t s, Rhs rb) {
   const double diag = mass + 4.0;
   if (g.tiled) {
     switch (out.prec) {
-      case P_F64: launch(k_residual<P_F64, true>, g, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
-      case P_F32: launch(k_residual<P_F32, true>, g, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
-      case P_I8: launch(k_residual<P_I8, true>, g, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
-      case P_BF16: launch(k_residual<P_BF16, true>, g, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
-      default: launch(k_residual<P_F16, true>, g, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
+      case P_F64: launch_n(k_residual<P_F64, true>, g, rb.n, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials, rb); break;
+      case P_F32: launch_n(k_residual<P_F32, true>, g, rb.n, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials, rb); break;
+      case P_I8: launch_n(k_residual<P_I8, true>, g, rb.n, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials, rb); break;
+      case P_BF16: launch_n(k_residual<P_BF16, true>, g, rb.n, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials, rb); break;
+      default: launch_n(k_residual<P_F16, true>, g, rb.n, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials, rb); break;
     }
   } else {
     switch (out.prec) {
-      case P_F64: launch(k_residual<P_F64, false>, g, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
-      case P_F32: launch(k_residual<P_F32, false>, g, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
-      case P_I8: launch(k_residual<P_I8, false>, g, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
-      case P_BF16: launch(k_residual<P_BF16, false>, g, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
-      default: launch(k_residual<P_F16, false>, g, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials); break;
+      case P_F64: launch_n(k_residual<P_F64, false>, g, rb.n, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials, rb); break;
+      case P_F32: launch_n(k_residual<P_F32, false>, g, rb.n, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials, rb); break;
+      case P_I8: launch_n(k_residual<P_I8, false>, g, rb.n, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials, rb); break;
+      case P_BF16: launch_n(k_residual<P_BF16, false>, g, rb.n, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials, rb); break;
+      default: launch_n(k_residual<P_F16, false>, g, rb.n, s, nullptr, g, U64, t64, b64, out, diag, gate, fin, st, partials, rb); break;
     }
   }
-  launch_finalize(g, partials, st, fin, gate, s);
+  launch_finalize(g, partials, st, fin, gate, s, rb);
 }
 
 void launch_p_update(const Geom& g, SpinorBuf r, SpinorBuf p, SolverState* st, hipStream_t s, const EventPair* ev) {

@@ -33,9 +33,43 @@ __device__ __forceinline__ double block_sum(double v) {
 // the cross-workgroup step in its own launch avoids device-scope
 // acquire/release per workgroup, which on a multi-XCD part writes back and
 // invalidates the XCD's L2 and would throw away the stencil's neighbour reuse.
-__device__ __forceinline__ void store_partial(double v, double* partials) {
+__device__ __forceinline__ void store_partial(double v, double* partials, int index) {
   const double bs = block_sum(v);
-  if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+  if (threadIdx.x == 0) partials[index] = bs;
+}
+__device__ __forceinline__ void store_partial(double v, double* partials) { store_partial(v, partials, blockIdx.x); }
+
+// ---- several systems per launch (Rhs): system k's buffers are offset by
+// k * stride bytes.
+template <class T>
+__device__ __forceinline__ T* rhs_shift(T* p, long long off) {
+  return p ? reinterpret_cast<T*>(reinterpret_cast<char*>(p) + off) : p;
+}
+template <class T>
+__device__ __forceinline__ const T* rhs_shift(const T* p, long long off) {
+  return p ? reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + off) : p;
+}
+__device__ __forceinline__ SpinorBuf rhs_shift(SpinorBuf b, long long off) {
+  b.data = rhs_shift(static_cast<char*>(b.data), off);
+  b.scale = rhs_shift(b.scale, off);
+  return b;
+}
+__device__ __forceinline__ RingBuf rhs_shift(RingBuf r, long long off) {
+  r.data = rhs_shift(r.data, off);
+  r.scale = rhs_shift(r.scale, off);
+  return r;
+}
+// Split a workgroup index L over n systems, system fastest: the n systems
+// of one tile run back to back (on one XCD, after xcd_tile), so that the
+// tile's links are read from HBM once for all of them.
+__device__ __forceinline__ int rhs_split(int L, const Rhs& rb, int& k) {
+  if (rb.n == 1) {
+    k = 0;
+    return L;
+  }
+  const int T = L / rb.n;
+  k = L - T * rb.n;
+  return T;
 }
 
 __device__ __forceinline__ bool gate_open(const SolverState* st, int gate) {

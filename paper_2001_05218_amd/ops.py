@@ -90,7 +90,8 @@ def wilson_force(a: torch.Tensor, b: torch.Tensor, coeff: float = 1.0, out: torc
 
 
 def make_params(tol=1e-10, max_iter=10000, inner="f64", reliable_interval=50, rhs="source", io_dtype=WD_C128,
-                zero_guess=True, history_len=0, profile=False, scheme="reliable", inner_tol=0.0, ring_len=0):
+                zero_guess=True, history_len=0, profile=False, scheme="reliable", inner_tol=0.0, ring_len=0,
+                schedule="auto"):
     p = _lib.WdCgParams()
     p.tol = float(tol)
     p.max_iter = int(max_iter)
@@ -108,6 +109,8 @@ def make_params(tol=1e-10, max_iter=10000, inner="f64", reliable_interval=50, rh
     p.scheme = {"reliable": 0, "refinement": 1}[scheme] if isinstance(scheme, str) else int(scheme)
     p.inner_tol = float(inner_tol)
     p.ring_len = int(ring_len)
+    p.batch_schedule = ({"auto": _lib.WD_BATCH_AUTO, "persistent": _lib.WD_BATCH_PERSISTENT,
+                         "lockstep": _lib.WD_BATCH_LOCKSTEP}[schedule] if isinstance(schedule, str) else int(schedule))
     return p, hist
 
 
@@ -162,9 +165,12 @@ def cg_solve(U: torch.Tensor, b: torch.Tensor, mass: float, tol: float = 1e-10, 
 def cg_solve_batched(U: torch.Tensor, B: torch.Tensor, mass: float, tol: float = 1e-10, max_iter: int = 10000,
                      reliable_interval: int = 50, rhs: str = "source", X0: torch.Tensor | None = None,
                      workspace: torch.Tensor | None = None, raise_on_nonconvergence: bool = True,
-                     inner: str = "f32"):
-    """Solve nrhs systems sharing U in one persistent launch. B: (nrhs, Lt, Lz, Ly, Lx, 4, 3).
-    inner: storage of the inner vectors ("f32", "bf16", "f16" or "i8"; FP32 arithmetic)."""
+                     inner: str = "f32", schedule: str = "auto"):
+    """Solve nrhs systems sharing U. B: (nrhs, Lt, Lz, Ly, Lx, 4, 3).
+    inner: storage of the inner vectors ("f32", "bf16", "f16" or "i8"; FP32 arithmetic).
+    schedule: "persistent" (one cooperative launch for the whole solve), "lockstep" (each CG
+    step one launch over all systems; "bf16", "f16" or "i8" storage, extents multiples of 4)
+    or "auto" (lockstep where it applies)."""
     dims = dims_of_spinor(B)
     if B.dim() != 7:
         raise ValueError("B must be (nrhs, Lt, Lz, Ly, Lx, 4, 3)")
@@ -172,7 +178,7 @@ def cg_solve_batched(U: torch.Tensor, B: torch.Tensor, mass: float, tol: float =
     _need(B, "B", (torch.complex128, torch.complex64))
     _need(U, "U", (torch.complex128,), gauge_shape(dims))
     io = WD_C64 if B.dtype == torch.complex64 else WD_C128
-    params, _ = make_params(tol, max_iter, inner, reliable_interval, rhs, io, X0 is None, 0)
+    params, _ = make_params(tol, max_iter, inner, reliable_interval, rhs, io, X0 is None, 0, schedule=schedule)
     X = torch.empty_like(B) if X0 is None else X0.clone()
     need = workspace_bytes(dims, params, nrhs)
     if workspace is None or workspace.numel() < need:

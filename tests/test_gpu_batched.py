@@ -90,18 +90,20 @@ def test_not_converged_reports_partial():
         assert abs(res - infos[k]["true_rel_res"]) <= 1e-12
 
 
-@pytest.mark.parametrize("inner", ["f32", "f16", "bf16", "i8"])
-def test_config3_24x24x24x48_sixteen_sources(inner):
+@pytest.mark.parametrize("inner,schedule", [("f32", "persistent"), ("f16", "persistent"), ("bf16", "persistent"),
+                                            ("i8", "persistent"), ("f16", "lockstep"), ("bf16", "lockstep"),
+                                            ("i8", "lockstep")])
+def test_config3_24x24x24x48_sixteen_sources(inner, schedule):
     """Full-size batched workload: 12 point sources at the origin + 4 Gaussian,
     Haar links, m = 0.05; every system's FP64 true residual <= 1e-10, and the
     oracle's residual at sampled sites of two systems. Far from a point source
     the inner vectors fall below FP32's normal range, which the scaled
     storages (FP16, int8) must survive."""
     dims, mass = (24, 24, 24, 48), 0.05
-    log(f"batched 24^3x48 x16 {inner}")
+    log(f"batched 24^3x48 x16 {inner} {schedule}")
     U = fieldgen.gauge_field(dims, "haar", 200105248)
     B = _sources(dims, 4, 200105249)
-    X, infos = wd.cg_solve_batched(to_dev(U), to_dev(B), mass, tol=TOL, inner=inner)
+    X, infos = wd.cg_solve_batched(to_dev(U), to_dev(B), mass, tol=TOL, inner=inner, schedule=schedule)
     its = [i["iterations"] for i in infos]
     log(f"  iterations {its} seconds {infos[0]['seconds']:.3f}")
     assert all(i["true_rel_res"] <= TOL for i in infos)
@@ -131,3 +133,63 @@ def test_low_precision_storage(inner, dims):
         assert res <= TOL * (1 + 1e-3), (inner, k, res)
         assert abs(res - infos[k]["true_rel_res"]) <= 1e-13
         assert infos[k]["reliable_updates"] >= 1
+
+
+# ---- lockstep schedule: the single-system mixed kernels over all systems at once
+
+@pytest.mark.parametrize("inner", ["bf16", "f16", "i8"])
+def test_lockstep_each_system_matches_single_solve(inner):
+    # near-identity links (two-row links in the inner loop), Gaussian sources
+    dims, mass = (8, 8, 8, 8), 0.05
+    log(f"lockstep {inner} 8^4 x5")
+    U = fieldgen.gauge_field(dims, "near_identity", 351)
+    B = fieldgen.gaussian_spinor(dims, 352, nrhs=5)
+    Ut = to_dev(U)
+    X, infos = wd.cg_solve_batched(Ut, to_dev(B), mass, tol=TOL, inner=inner, schedule="lockstep")
+    Xn = to_np(X)
+    for k in range(5):
+        res = oracle.true_relative_residual(U, Xn[k], B[k], mass)
+        assert res <= TOL * (1 + 1e-3), (k, res)
+        assert abs(res - infos[k]["true_rel_res"]) <= 1e-13
+        assert infos[k]["two_row_links"] == 1 and infos[k]["reliable_updates"] >= 1
+        xs, si = wd.cg_solve(Ut, to_dev(B[k]), mass, tol=TOL, inner=inner)
+        # the same kernels, arithmetic and reduction order as a single solve of system k
+        assert infos[k]["iterations"] == si["iterations"]
+        assert np.array_equal(Xn[k], to_np(xs))
+
+
+def test_lockstep_point_sources_masks_and_c64():
+    # point and Gaussian sources stop at different iterations: the converged
+    # systems' gates close while the rest continue
+    dims, mass = (4, 4, 4, 8), 0.05
+    U = fieldgen.gauge_field(dims, "haar", 361)
+    B = _sources(dims, 4, 362).astype(np.complex64)
+    X, infos = wd.cg_solve_batched(to_dev(U), to_dev(B), mass, tol=TOL, inner="f16", schedule="lockstep")
+    assert X.dtype == torch.complex64
+    its = [i["iterations"] for i in infos]
+    log(f"  lockstep iterations per rhs {its}")
+    Xn = to_np(X).astype(np.complex128)
+    for k in range(16):
+        assert infos[k]["true_rel_res"] <= TOL
+        xr, _ = oracle.cgnr(U, B[k].astype(np.complex128), mass, tol=1e-12)
+        assert rel(Xn[k], xr) <= 2e-6
+
+
+def test_lockstep_normal_mode_initial_guess_and_partial():
+    dims, mass = (4, 8, 4, 8), 0.1
+    U = fieldgen.gauge_field(dims, "near_identity", 371)
+    B = fieldgen.gaussian_spinor(dims, 372, nrhs=3)
+    X0 = 0.1 * fieldgen.gaussian_spinor(dims, 373, nrhs=3)
+    X, infos = wd.cg_solve_batched(to_dev(U), to_dev(B), mass, tol=TOL, inner="i8", rhs="normal",
+                                   X0=to_dev(X0), schedule="lockstep")
+    Xn = to_np(X)
+    for k in range(3):
+        assert oracle.true_relative_residual(U, Xn[k], B[k], mass, rhs="normal") <= TOL * (1 + 1e-3)
+    # max_iter reached: every system reports its last iterate and its true residual
+    X, infos = wd.cg_solve_batched(to_dev(U), to_dev(B), mass, tol=TOL, inner="bf16", max_iter=7,
+                                   raise_on_nonconvergence=False, schedule="lockstep")
+    Xn = to_np(X)
+    for k in range(3):
+        assert infos[k]["status"] == 1 and infos[k]["iterations"] == 7
+        res = oracle.true_relative_residual(U, Xn[k], B[k], mass)
+        assert abs(res - infos[k]["true_rel_res"]) <= 1e-12

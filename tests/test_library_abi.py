@@ -38,7 +38,7 @@ def test_required_boundary_calls_present():
 def test_struct_layouts_match_header():
     # sizes of the structs as laid out by a C compiler for the header
     assert ctypes.sizeof(_lib.WdLattice) == 16
-    assert ctypes.sizeof(_lib.WdCgParams) == 64
+    assert ctypes.sizeof(_lib.WdCgParams) == 72
     assert ctypes.sizeof(_lib.WdCgResult) == 64
 
 
@@ -59,6 +59,7 @@ def _params(**kw):
     p.scheme = kw.get("scheme", 0)
     p.inner_tol = kw.get("inner_tol", 0.0)
     p.ring_len = kw.get("ring_len", 0)
+    p.batch_schedule = kw.get("batch_schedule", 0)
     return p
 
 
@@ -199,6 +200,28 @@ def test_batched_rejects_fp64_inner_and_sizes_by_storage(lib):
     rc = lib.cg_solve_batched(lat, 0.1, 1, 4, 2, 3, ctypes.byref(f64), None, 4, 1 << 40, None)
     assert rc == _lib.WD_ERR_INVALID
     assert "inner_prec" in _lib.last_error()
-    sizes = {prec: lib.wd_workspace_bytes(lat, ctypes.byref(_params(inner_prec=prec)), 16) for prec in (1, 2, 3, 4)}
+    persistent = _lib.WD_BATCH_PERSISTENT
+    sizes = {prec: lib.wd_workspace_bytes(lat, ctypes.byref(_params(inner_prec=prec, batch_schedule=persistent)), 16)
+             for prec in (1, 2, 3, 4)}
     # p, r, t shrink with the storage (FP32 > FP16 with scales > BF16 > int8 with scales)
     assert sizes[1] > sizes[3] > sizes[2] > sizes[4] > 0
+    # the lockstep schedule (the default for 16- and 8-bit storage on tileable
+    # lattices) keeps a ring of search directions per system: more memory
+    for prec in (2, 3, 4):
+        auto = lib.wd_workspace_bytes(lat, ctypes.byref(_params(inner_prec=prec)), 16)
+        lock = lib.wd_workspace_bytes(lat, ctypes.byref(_params(inner_prec=prec, batch_schedule=_lib.WD_BATCH_LOCKSTEP)), 16)
+        assert auto == lock > sizes[prec]
+
+
+def test_batched_lockstep_rejects(lib):
+    lock = _lib.WD_BATCH_LOCKSTEP
+    # FP32 storage, or a lattice that does not tile, or iterative refinement: no lockstep kernels
+    for lat, kw in ((_lat((8, 8, 8, 8)), dict(inner_prec=1)), (_lat((6, 8, 8, 8)), dict(inner_prec=3)),
+                    (_lat((8, 8, 8, 8)), dict(inner_prec=3, scheme=1))):
+        rc = lib.cg_solve_batched(lat, 0.1, 1, 4, 2, 3, ctypes.byref(_params(batch_schedule=lock, **kw)), None, 4,
+                                  1 << 40, None)
+        assert rc == _lib.WD_ERR_INVALID
+        assert "lockstep" in _lib.last_error()
+    rc = lib.cg_solve_batched(_lat((8, 8, 8, 8)), 0.1, 1, 4, 2, 3, ctypes.byref(_params(inner_prec=3, batch_schedule=7)),
+                              None, 4, 1 << 40, None)
+    assert rc == _lib.WD_ERR_INVALID and "batch_schedule" in _lib.last_error()
