@@ -190,6 +190,10 @@ def run_cpu_baseline(dims, fp64_iters):
 BATCHED_DIMS = (24, 24, 24, 48)
 BATCHED_LINK_B = 2 * 288
 BATCHED_VEC_B = {"f32": 96, "bf16": 48, "f16": 52, "i8": 28}
+# Lockstep schedule: per CG step D and D^+ read the two-row 16-bit links once
+# for all systems (2 x 4 x 6 complex half words); per system and iteration
+# p, t, r, t, r, r, p, p and the fold's p.
+LOCKSTEP_LINK_B = 2 * 96
 
 
 def batched_rhs_bytes(inner):
@@ -199,8 +203,9 @@ FORCE_BYTES = 2 * 192 + 4 * 9 * 16
 
 
 def bench_batched(dev):
-    """16 systems in one persistent launch, for each inner storage; the row
-    reports the fastest and lists all."""
+    """16 systems sharing one gauge field, for each schedule and inner storage
+    (persistent: one cooperative launch; lockstep: one launch per CG step over
+    all systems); the row reports the fastest and lists all."""
     import torch
     import fieldgen
     import paper_2001_05218_amd as wd
@@ -210,25 +215,34 @@ def bench_batched(dev):
     pts = fieldgen.point_sources(dims)[:12]
     gs = fieldgen.gaussian_spinor(dims, 200105249, nrhs=4)
     B = torch.from_numpy(np.concatenate([pts, gs]).astype(np.complex64)).to(dev)
-    p, _ = wd.ops.make_params(TOL, 20000, "f32", 50, "source", wd._lib.WD_C64, True, 0)
-    ws = torch.empty(wd.workspace_bytes(dims, p, 16), dtype=torch.uint8, device=dev)
+    combos = [("persistent", inner) for inner in ("f32", "f16", "bf16", "i8")] + \
+             [("lockstep", inner) for inner in ("f16", "bf16", "i8")]
+    need = 0
+    for sched, inner in combos:
+        p, _ = wd.ops.make_params(TOL, 20000, inner, 50, "source", wd._lib.WD_C64, True, 0, schedule=sched)
+        need = max(need, wd.workspace_bytes(dims, p, 16))
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
     variants = {}
-    for inner in ("f32", "f16", "bf16", "i8"):
-        wd.cg_solve_batched(U, B, 0.05, tol=TOL, workspace=ws, inner=inner)
+    for sched, inner in combos:
+        wd.cg_solve_batched(U, B, 0.05, tol=TOL, workspace=ws, inner=inner, schedule=sched)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        X, infos = wd.cg_solve_batched(U, B, 0.05, tol=TOL, workspace=ws, inner=inner)
+        X, infos = wd.cg_solve_batched(U, B, 0.05, tol=TOL, workspace=ws, inner=inner, schedule=sched)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         its = [i["iterations"] for i in infos]
-        alg = V * (BATCHED_LINK_B * max(its) + batched_rhs_bytes(inner) * sum(its))
-        variants[inner] = {"seconds": dt, "iterations_max": max(its), "iterations_mean": float(np.mean(its)),
-                           "true_rel_res_max": max(i["true_rel_res"] for i in infos),
-                           "site_rhs_iterations_per_s": V * sum(its) / dt, "algorithmic_GB_per_s": alg / dt / 1e9,
-                           "frac_hbm": alg / dt / 1e9 / HBM_PEAK_GBS}
+        if sched == "lockstep":
+            alg = V * (LOCKSTEP_LINK_B * max(its) + 9 * BATCHED_VEC_B[inner] * sum(its))
+        else:
+            alg = V * (BATCHED_LINK_B * max(its) + batched_rhs_bytes(inner) * sum(its))
+        variants[f"{sched}_{inner}"] = {
+            "schedule": sched, "inner": inner, "seconds": dt, "iterations_max": max(its),
+            "iterations_mean": float(np.mean(its)), "true_rel_res_max": max(i["true_rel_res"] for i in infos),
+            "site_rhs_iterations_per_s": V * sum(its) / dt, "algorithmic_GB_per_s": alg / dt / 1e9,
+            "frac_hbm": alg / dt / 1e9 / HBM_PEAK_GBS}
         del X
     best = min(variants, key=lambda k: variants[k]["seconds"])
-    out = {"inner": best, "nrhs": 16, "lattice_xyzt": list(dims), **variants[best], "variants": variants}
+    out = {"nrhs": 16, "lattice_xyzt": list(dims), **variants[best], "variants": variants}
     del U, B, ws
     return out
 

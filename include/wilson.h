@@ -181,18 +181,29 @@ int cg_solve(const wd_lattice* lat, double mass, const void* U, const void* b, v
              const wd_cg_params* params, wd_cg_result* result, void* workspace, size_t ws_bytes, void* stream);
 
 /*
- * Solve nrhs systems sharing one gauge field in ONE persistent cooperative
- * launch. B, X: device, (nrhs, Lt, Lz, Ly, Lx, 4, 3) of element type
- * params->io_dtype. Inner iterations run in FP32 arithmetic with every link
- * load (FP32 links) reused across all right-hand sides; p, r and t are stored
- * in params->inner_prec (WD_F32, WD_BF16, WD_F16 or WD_I8; WD_F64 is rejected)
- * and the solution increment in FP32. Each system carries its own alpha, beta
- * and convergence mask; FP64 reliable updates (every
- * params->reliable_interval iterations, and whenever a system's residual has
- * fallen by params->inner_tol, default as for cg_solve) recompute each
- * residual from an FP64 solution. results: host array of nrhs entries (may be NULL).
- * 1 <= nrhs <= 16. Blocks until all systems end. Returns WD_OK if every
- * system converged, WD_NOT_CONVERGED if any did not, or a WD_ERR_* code.
+ * Solve nrhs systems sharing one gauge field (the batched multi-RHS form of
+ * the mixed-precision CG, Sec. 2 and Sec. 3.2 applied per system).
+ * B, X: device, (nrhs, Lt, Lz, Ly, Lx, 4, 3) of element type params->io_dtype.
+ * Inner iterations run in FP32 arithmetic; p, r and t are stored in
+ * params->inner_prec (WD_F32, WD_BF16, WD_F16 or WD_I8; WD_F64 is rejected).
+ * Each system carries its own alpha, beta and convergence mask; FP64 reliable
+ * updates (every params->reliable_interval iterations, and whenever a
+ * system's residual has fallen by params->inner_tol, default as for cg_solve)
+ * recompute each residual from an FP64 solution.
+ * params->batch_schedule selects how (see WD_BATCH_*):
+ *   persistent  ONE cooperative launch for the whole solve; FP32 links staged
+ *               in LDS per 64-site block and reused by every system; the
+ *               solution increment in FP32.
+ *   lockstep    cg_solve's mixed-precision kernels, each CG step one launch over
+ *               all systems (tile-major, so a tile's links are fetched from HBM
+ *               once per step for all systems); each system's iterates equal
+ *               those of cg_solve on it alone. BF16 / FP16 / int8 storage,
+ *               reliable updates, lattice extents multiples of 4 (else
+ *               WD_ERR_INVALID); more workspace (a ring of search directions
+ *               per system).
+ * results: host array of nrhs entries (may be NULL). 1 <= nrhs <= 16. Blocks
+ * until all systems end. Returns WD_OK if every system converged,
+ * WD_NOT_CONVERGED if any did not, or a WD_ERR_* code.
  */
 int cg_solve_batched(const wd_lattice* lat, double mass, const void* U, int32_t nrhs, const void* B, void* X,
                      const wd_cg_params* params, wd_cg_result* results, void* workspace, size_t ws_bytes,
