@@ -36,6 +36,11 @@
  * or a negative WD_ERR_* code; wd_last_error() returns a message for the
  * calling thread's last non-zero return. Argument errors are detected before
  * any device work is issued. Nothing aborts or throws across the ABI.
+ *
+ * Threads: the blocking solvers (cg_solve, cg_solve_batched, laplace_cg_solve)
+ * share pinned host buffers per device, so their calls on one device are
+ * serialised (a second thread's call waits for the first to return). The
+ * current device (hipSetDevice) selects the GPU.
  */
 #ifndef WILSON_MI355X_H
 #define WILSON_MI355X_H

@@ -247,6 +247,19 @@ bool use_lockstep(const Geom& g, const wd_cg_params* p) {
   return p->batch_schedule == WD_BATCH_LOCKSTEP || (p->batch_schedule == WD_BATCH_AUTO && lockstep_possible(g, p));
 }
 
+// The blocking solvers share per-device pinned state mirrors and event sets,
+// so solves on one device are serialised: a call from a second host thread
+// waits until the first has returned.
+std::mutex g_solve_mu[64];
+
+int lock_device(std::unique_lock<std::mutex>& lk) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(WD_ERR_HIP, "device index %d out of range", dev);
+  lk = std::unique_lock<std::mutex>(g_solve_mu[dev]);
+  return WD_OK;
+}
+
 // Host mirrors of the device state, pinned, one pair per device.
 struct HostMirror {
   SolverState* buf[2] = {nullptr, nullptr};
@@ -1110,6 +1123,8 @@ extern "C" int laplace_cg_solve(const wd_lattice* lat, double m2, const void* U,
   const size_t need = layout_lap(nullptr, g, params->history_len).bytes;
   if (!workspace || ws_bytes < need)
     return fail(WD_ERR_WORKSPACE, "workspace of %zu bytes given, %zu needed", workspace ? ws_bytes : 0, need);
+  std::unique_lock<std::mutex> lk;
+  if ((rc = lock_device(lk))) return rc;
   return lap_cg(g, m2, U, b, x, params, result, workspace, as_stream(stream), t0);
 }
 
@@ -1129,6 +1144,8 @@ extern "C" int cg_solve(const wd_lattice* lat, double mass, const void* U, const
   if (!workspace || ws_bytes < need)
     return fail(WD_ERR_WORKSPACE, "workspace of %zu bytes given, %zu needed", workspace ? ws_bytes : 0, need);
   const hipStream_t s = as_stream(stream);
+  std::unique_lock<std::mutex> lk;
+  if ((rc = lock_device(lk))) return rc;
   if (params->inner_prec == WD_F64) return cg_plain(g, mass, U, b, x, params, result, workspace, s, t0);
   return cg_mixed(g, mass, U, b, x, params, result, workspace, s, t0);
 }
@@ -1154,8 +1171,11 @@ extern "C" int cg_solve_batched(const wd_lattice* lat, double mass, const void* 
   if (params->batch_schedule == WD_BATCH_LOCKSTEP && !lockstep_possible(g, params))
     return fail(WD_ERR_INVALID, "lockstep batching needs BF16, FP16 or int8 inner storage, reliable updates "
                                 "and lattice extents that are multiples of 4");
-  if (use_lockstep(g, params))
+  if (use_lockstep(g, params)) {
+    std::unique_lock<std::mutex> lk;
+    if ((rc = lock_device(lk))) return rc;
     return cg_mixed_lockstep(g, mass, U, nrhs, B, X, params, results, workspace, as_stream(stream));
+  }
   char err[512] = {0};
   rc = batched_solve(g, mass, U, nrhs, B, X, params, results, workspace, as_stream(stream), err, sizeof(err));
   if (rc != WD_OK) return fail(rc, "%s", err);

@@ -254,3 +254,36 @@ def test_mixed_point_source_24x24x24x48(inner):
     rhs = oracle.wilson_D_sites(U, b, mass, sites, dagger=True)
     bn = np.linalg.norm(oracle.wilson_Ddag(U, b, mass))
     assert np.linalg.norm(lhs - rhs) <= TOL * bn
+
+
+def test_two_host_threads_solve_at_once():
+    # the blocking solvers share per-device pinned mirrors: calls from two
+    # threads (each on its own stream) are serialised and give the results of
+    # sequential calls, bit for bit
+    import threading
+    dims, mass = (8, 8, 8, 8), 0.05
+    U = to_dev(fieldgen.gauge_field(dims, "near_identity", 381))
+    inners = ["i8", "f64", "f16", "i8"]
+    bs = [to_dev(fieldgen.gaussian_spinor(dims, 382 + i)) for i in range(4)]
+    ref = [wd.cg_solve(U, b, mass, tol=1e-10, inner=inn)[0] for b, inn in zip(bs, inners)]
+    torch.cuda.synchronize()
+    out, errs = [None] * 4, []
+
+    def run(i):
+        try:
+            stream = torch.cuda.Stream()
+            with torch.cuda.stream(stream):
+                x, _ = wd.cg_solve(U, bs[i], mass, tol=1e-10, inner=inners[i])
+            stream.synchronize()
+            out[i] = x
+        except Exception as e:   # reported below
+            errs.append(e)
+
+    threads = [threading.Thread(target=run, args=(i,)) for i in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errs, errs
+    for i in range(4):
+        assert torch.equal(out[i], ref[i]), i
