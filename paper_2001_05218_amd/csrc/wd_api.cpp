@@ -168,11 +168,15 @@ struct LockstepWorkspace {
   size_t bytes;
 };
 
-// Ring slots per system: the single-system rule with the memory budget shared.
+// Ring slots per system: the single-system rule, with a budget of 16 GiB
+// shared by the systems (16 systems on 32^3 x 64: 16 slots each, a fold every
+// ~12 iterations; on 24^3 x 48: 31 slots, more than the reliable updates leave
+// pending).
+constexpr size_t kBatchRingBudget = size_t(16) << 30;
 int ring_length_batch(const wd_cg_params* p, const Geom& g, int nrhs) {
   if (p->ring_len > 0) return p->ring_len;
   const size_t per = align_up(spinor_bytes(p->inner_prec, g.Vpad)) + align_up(spinor_scale_bytes(p->inner_prec, g.Vpad));
-  const long long by_mem = (long long)(kRingBudget / ((size_t)nrhs * per));
+  const long long by_mem = (long long)(kBatchRingBudget / ((size_t)nrhs * per));
   const long long want = std::min<long long>((long long)reliable_interval_of(p) + kSlotEvery, by_mem);
   return (int)std::max<long long>(8, std::min<long long>(256, want));
 }
