@@ -696,18 +696,40 @@ __device__ __forceinline__ void outer_acc(const double u[12], const double v[12]
   }
 }
 
-// G_mu at site s (0 outside the lattice), 18 reals. Each of the four spinors is
-// loaded and projected in turn, so at most one full spinor is live.
+// Sites s0 .. s0 + n - 1 of a canonical spinor field into registers, one site
+// per thread, through LDS: the block's records form one contiguous range, read
+// with consecutive 16-byte words across the lanes and then transposed. A
+// thread reading its own 192-byte record directly would touch a cache line per
+// word for 16 useful bytes, and the force kernel was bound by exactly those
+// cache-line lookups. Threads of sites beyond the lattice get zeros.
+__device__ __forceinline__ void load_own(const double2* __restrict__ src, int s0, int n,
+                                         double2 (*stage)[kBlock + 1], double v[24]) {
+  const double2* base = src + (size_t)s0 * 12;
+  for (int q = threadIdx.x; q < n * 12; q += kBlock) {
+    const int site = q / 12;
+    stage[q - site * 12][site] = base[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int w = 0; w < 12; ++w) {
+    const double2 d = (int)threadIdx.x < n ? stage[w][threadIdx.x] : make_double2(0.0, 0.0);
+    v[2 * w] = d.x;
+    v[2 * w + 1] = d.y;
+  }
+  __syncthreads();   // the stage is rewritten next
+}
+
+// G_mu at a site whose own spinors a(x), b(x) are in registers; the
+// neighbours a(x + mu), b(x + mu) are read from memory. 18 reals.
 template <int MU>
-__device__ __forceinline__ void force_site(const CanonSpinor& a, const CanonSpinor& b, int s, int sf, double f[18]) {
+__device__ __forceinline__ void force_site(const double aown[24], const double bown[24], const CanonSpinor& a,
+                                           const CanonSpinor& b, int sf, double f[18]) {
   double psi[24], h[12], k[12];
-  a.load(s, psi);
-  project<MU, -1>(psi, h);    // (1 - g) a(x), upper half
+  project<MU, -1>(aown, h);   // (1 - g) a(x), upper half
   b.load(sf, psi);
   project<MU, -1>(psi, k);    // matching combination of b(x + mu)
   outer_acc(h, k, f);
-  b.load(s, psi);
-  project<MU, +1>(psi, h);    // (1 + g) b(x)
+  project<MU, +1>(bown, h);   // (1 + g) b(x)
   a.load(sf, psi);
   project<MU, +1>(psi, k);    // (1 + g) a(x + mu)
   outer_acc(h, k, f);
@@ -718,13 +740,14 @@ __device__ __forceinline__ void force_site(const CanonSpinor& a, const CanonSpin
 // coalesced range of F (a thread's own 144-byte record would otherwise be
 // written as nine 16-byte pieces 144 bytes apart from its neighbours').
 template <int MU>
-__device__ __forceinline__ void force_dir(Geom g, const CanonSpinor& a, const CanonSpinor& b, double c, int accumulate,
-                                          double2* __restrict__ F, int s0, const Nbrs& nb, double2 (*stage)[kBlock]) {
+__device__ __forceinline__ void force_dir(Geom g, const double aown[24], const double bown[24], const CanonSpinor& a,
+                                          const CanonSpinor& b, double c, int accumulate, double2* __restrict__ F,
+                                          int s0, const Nbrs& nb, double2 (*stage)[kBlock + 1]) {
   const int s = s0 + threadIdx.x;
   double f[18];
 #pragma unroll
   for (int i = 0; i < 18; ++i) f[i] = 0.0;
-  if (s < g.V) force_site<MU>(a, b, s, nb.fwd[MU], f);
+  if (s < g.V) force_site<MU>(aown, bown, a, b, nb.fwd[MU], f);
 #pragma unroll
   for (int e = 0; e < 9; ++e) stage[e][threadIdx.x] = make_double2(c * f[2 * e], c * f[2 * e + 1]);
   __syncthreads();
@@ -744,15 +767,21 @@ __device__ __forceinline__ void force_dir(Geom g, const CanonSpinor& a, const Ca
 
 __global__ __launch_bounds__(kBlock) void k_force(Geom g, CanonSpinor a, CanonSpinor b, double coeff, int accumulate,
                                                   double2* __restrict__ F) {
-  __shared__ double2 stage[9][kBlock];
+  // rows padded by one word: the transposing writes of consecutive words of a
+  // record then fall in different banks
+  __shared__ double2 stage[12][kBlock + 1];
   const int s0 = blockIdx.x * kBlock;
+  const int n = min(kBlock, g.V - s0);
   const int s = s0 + threadIdx.x;
   const Nbrs nb = neighbours(g, s < g.V ? s : s0);
   const double c = 0.5 * coeff;
-  force_dir<0>(g, a, b, c, accumulate, F, s0, nb, stage);
-  force_dir<1>(g, a, b, c, accumulate, F, s0, nb, stage);
-  force_dir<2>(g, a, b, c, accumulate, F, s0, nb, stage);
-  force_dir<3>(g, a, b, c, accumulate, F, s0, nb, stage);
+  double aown[24], bown[24];
+  load_own(a.data, s0, n, stage, aown);
+  load_own(b.data, s0, n, stage, bown);
+  force_dir<0>(g, aown, bown, a, b, c, accumulate, F, s0, nb, stage);
+  force_dir<1>(g, aown, bown, a, b, c, accumulate, F, s0, nb, stage);
+  force_dir<2>(g, aown, bown, a, b, c, accumulate, F, s0, nb, stage);
+  force_dir<3>(g, aown, bown, a, b, c, accumulate, F, s0, nb, stage);
 }
 
 __global__ void k_init_state(SolverState* st, double tol, int interval, double delta, double* hist,
