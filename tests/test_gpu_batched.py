@@ -137,17 +137,17 @@ def test_low_precision_storage(inner, dims):
 
 # ---- lockstep schedule: the single-system mixed kernels over all systems at once
 
-@pytest.mark.parametrize("inner", ["bf16", "f16", "i8"])
-def test_lockstep_each_system_matches_single_solve(inner):
+@pytest.mark.parametrize("inner,nrhs", [("bf16", 5), ("f16", 5), ("i8", 5), ("i8", 1)])
+def test_lockstep_each_system_matches_single_solve(inner, nrhs):
     # near-identity links (two-row links in the inner loop), Gaussian sources
     dims, mass = (8, 8, 8, 8), 0.05
-    log(f"lockstep {inner} 8^4 x5")
+    log(f"lockstep {inner} 8^4 x{nrhs}")
     U = fieldgen.gauge_field(dims, "near_identity", 351)
-    B = fieldgen.gaussian_spinor(dims, 352, nrhs=5)
+    B = fieldgen.gaussian_spinor(dims, 352, nrhs=nrhs)
     Ut = to_dev(U)
     X, infos = wd.cg_solve_batched(Ut, to_dev(B), mass, tol=TOL, inner=inner, schedule="lockstep")
     Xn = to_np(X)
-    for k in range(5):
+    for k in range(nrhs):
         res = oracle.true_relative_residual(U, Xn[k], B[k], mass)
         assert res <= TOL * (1 + 1e-3), (k, res)
         assert abs(res - infos[k]["true_rel_res"]) <= 1e-13
