@@ -7,6 +7,7 @@ import torch
 import fieldgen
 import oracle
 from gpu_util import log, rel, to_dev, to_np
+from paper_2001_05218_amd import _lib
 
 pytestmark = pytest.mark.gpu
 
@@ -193,3 +194,21 @@ def test_lockstep_normal_mode_initial_guess_and_partial():
         assert infos[k]["status"] == 1 and infos[k]["iterations"] == 7
         res = oracle.true_relative_residual(U, Xn[k], B[k], mass)
         assert abs(res - infos[k]["true_rel_res"]) <= 1e-12
+
+
+def test_lockstep_zero_and_nan_systems():
+    # a zero source converges at once (x = 0) while the others iterate; a NaN
+    # in one source ends the call with WD_ERR_NAN
+    dims, mass = (4, 4, 4, 8), 0.1
+    U = fieldgen.gauge_field(dims, "haar", 391)
+    B = fieldgen.gaussian_spinor(dims, 392, nrhs=4)
+    B[1] = 0.0
+    X, infos = wd.cg_solve_batched(to_dev(U), to_dev(B), mass, tol=TOL, inner="f16", schedule="lockstep")
+    Xn = to_np(X)
+    assert infos[1]["iterations"] == 0 and np.abs(Xn[1]).max() == 0.0
+    for k in (0, 2, 3):
+        assert oracle.true_relative_residual(U, Xn[k], B[k], mass) <= TOL * (1 + 1e-3)
+    B[2, 0, 1, 2, 3, 1, 2] = np.nan
+    with pytest.raises(_lib.WilsonError) as e:
+        wd.cg_solve_batched(to_dev(U), to_dev(B), mass, tol=TOL, inner="f16", schedule="lockstep")
+    assert e.value.code == _lib.WD_ERR_NAN
