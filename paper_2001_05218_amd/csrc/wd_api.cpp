@@ -113,6 +113,17 @@ int reliable_interval_of(const wd_cg_params* p) {
   return p->reliable_interval > 0 ? p->reliable_interval : 50;
 }
 
+// Besides every `interval` iterations, a mixed solve recomputes the residual
+// whenever the iterated residual has fallen by this factor since the last
+// update, so that the low-precision drift (~ unit roundoff x the residual at
+// the last update) stays well below the residual being iterated.
+double reliable_delta(const wd_cg_params* p) {
+  if (p->inner_tol > 0.0) return p->inner_tol;
+  if (p->scheme == WD_ITERATIVE_REFINEMENT) return 0.1;
+  const int P = p->inner_prec;
+  return (P == WD_BF16 || P == WD_I8) ? 0.1 : (P == WD_F16) ? 1e-2 : 1e-4;
+}
+
 // Ring slots: the caller's ring_len, else enough that the ring is folded only
 // at reliable updates (interval + kSlotEvery), within kRingBudget bytes.
 int ring_length(const wd_cg_params* p, const Geom& g) {
@@ -722,13 +733,7 @@ int cg_mixed(const Geom& g, double mass, const void* U, const void* b, void* x, 
   // refinement: no periodic recomputation, only after each inner solve
   const int interval = reliable_interval_of(p);
   const CgWorkspace w = layout_cg(ws, g, P, p->history_len, ring_length(p, g));
-  // Besides every `interval` iterations, recompute the residual whenever the
-  // iterated residual has fallen by `delta` since the last update, so that
-  // the low-precision drift (~ unit roundoff x the residual at the last
-  // update) stays well below the residual being iterated.
-  double delta = (P == WD_BF16 || P == WD_I8) ? 0.1 : (P == WD_F16) ? 1e-2 : 1e-4;
-  if (refine) delta = 0.1;
-  if (p->inner_tol > 0.0) delta = p->inner_tol;
+  const double delta = reliable_delta(p);
   int rc = cg_setup(g, mass, U, b, x, p, w, interval, delta, w.rh, s);
   if (refine) launch_set_restart(w.st, s);
   if (rc) return rc;
@@ -852,8 +857,7 @@ int cg_mixed_lockstep(const Geom& g, double mass, const void* U, int nrhs, const
   const LockstepWorkspace L = layout_lockstep(ws, g, P, ring_length_batch(p, g, nrhs), nrhs);
   const CgWorkspace& w = L.sys0;
   const Rhs rb{nrhs, L.stride};
-  double delta = (P == WD_BF16 || P == WD_I8) ? 0.1 : (P == WD_F16) ? 1e-2 : 1e-4;
-  if (p->inner_tol > 0.0) delta = p->inner_tol;
+  const double delta = reliable_delta(p);
   const int c64 = p->io_dtype == WD_C64;
   const size_t io_stride = (size_t)g.V * 12 * (c64 ? 8 : 16);
   wd_cg_params q = *p;   // per-system set-up, without a residual history
