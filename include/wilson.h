@@ -163,7 +163,9 @@ int wilson_apply_dagger(const wd_lattice* lat, double mass, const void* U, const
 
 /*
  * Device workspace needed by cg_solve (nrhs = 1) or cg_solve_batched
- * (nrhs = number of right-hand sides) for these parameters, in bytes.
+ * (nrhs = number of right-hand sides) for these parameters, in bytes
+ * (for batched solves it depends on params->batch_schedule: the lockstep
+ * schedule keeps a ring of search directions per system).
  * Returns 0 on an invalid argument (see wd_last_error()).
  */
 size_t wd_workspace_bytes(const wd_lattice* lat, const wd_cg_params* params, int32_t nrhs);
