@@ -225,3 +225,17 @@ def test_batched_lockstep_rejects(lib):
     rc = lib.cg_solve_batched(_lat((8, 8, 8, 8)), 0.1, 1, 4, 2, 3, ctypes.byref(_params(inner_prec=3, batch_schedule=7)),
                               None, 4, 1 << 40, None)
     assert rc == _lib.WD_ERR_INVALID and "batch_schedule" in _lib.last_error()
+
+
+def test_lockstep_workspace_grows_by_one_region_per_system(lib):
+    # shared links and state copies once, then one equal region per system
+    # (with ring_len fixed, so the shared ring budget does not change the ring)
+    lat = _lat((8, 8, 8, 16))
+    lock = _lib.WD_BATCH_LOCKSTEP
+    sizes = [lib.wd_workspace_bytes(lat, ctypes.byref(_params(inner_prec=3, batch_schedule=lock, ring_len=16)), n)
+             for n in range(1, 17)]
+    steps = {b - a for a, b in zip(sizes, sizes[1:])}
+    assert len(steps) == 1
+    step = steps.pop()
+    assert step % 256 == 0 and step > 0
+    assert sizes[0] > step   # the shared part comes on top of system 0's region
