@@ -232,6 +232,35 @@ def finite_termination_residual(mass=0.1, seed=3) -> float:
     return oracle.true_relative_residual(U, x, b, mass)
 
 
+def residual_checker_errors(dims, mass, rhs="source", seed=21, c=0.5, eps=1e-3) -> dict:
+    """Errors of ``oracle.true_relative_residual`` against what linearity fixes.
+
+    With x_d the dense direct solution of the normal system (D^+ D x_d = b',
+    b' = D^+ b or b) the residual of c x_d is (1 - c) b', so the relative
+    residual is exactly |1 - c|; x = 0 gives exactly 1; and x_d + eps v
+    leaves the residual -eps D^+ D v, whose norm comes from the dense matrix
+    (not from the stencil the checker uses).
+    """
+    U = fieldgen.gauge_field(dims, "haar", seed)
+    b = fieldgen.gaussian_spinor(dims, seed + 1)
+    v = fieldgen.gaussian_spinor(dims, seed + 2)
+    D = oracle.dense_D(U, mass, dims)
+    M = D.conj().T @ D
+    bv = b.reshape(-1)
+    bp = D.conj().T @ bv if rhs == "source" else bv
+    xd = np.linalg.solve(M, bp).reshape(b.shape)
+    f = oracle.true_relative_residual
+    scaled = f(U, c * xd, b, mass, rhs=rhs)
+    zero = f(U, np.zeros_like(b), b, mass, rhs=rhs)
+    expect = eps * np.linalg.norm(M @ v.reshape(-1)) / np.linalg.norm(bp)
+    pert = f(U, xd + eps * v, b, mass, rhs=rhs)
+    return {
+        "scaled": abs(scaled - abs(1.0 - c)),
+        "zero": abs(zero - 1.0),
+        "perturbed": abs(pert - expect) / expect,
+    }
+
+
 # --------------------------------------------------------------- force
 
 def loss_dense(D, phi):

@@ -199,6 +199,33 @@ def test_cg_reports_true_residual():
     assert abs(info["true_rel_res"] - lap.true_relative_residual(U, x, b, 0.1)) < 1e-15
 
 
+def residual_checker_errors(dims, m2, seed=81, c=0.5, eps=1e-3, checker=None) -> dict:
+    """``lap.true_relative_residual`` against linearity: with x_d the dense
+    solution of L x = b, c x_d leaves (1 - c) b (relative residual |1 - c|),
+    x = 0 leaves b (exactly 1), and x_d + eps v leaves -eps L v, whose norm
+    comes from the dense matrix."""
+    f = checker or lap.true_relative_residual
+    U = fieldgen.gauge_field(dims, "haar", seed)
+    b = _colour_field(dims, seed + 1)
+    v = _colour_field(dims, seed + 2)
+    A = lap.dense_laplace(U, m2, dims)
+    xd = np.linalg.solve(A, b.reshape(-1)).reshape(b.shape)
+    expect = eps * np.linalg.norm(A @ v.reshape(-1)) / np.linalg.norm(b)
+    return {
+        "scaled": abs(f(U, c * xd, b, m2) - abs(1.0 - c)),
+        "zero": abs(f(U, np.zeros_like(b), b, m2) - 1.0),
+        "perturbed": abs(f(U, xd + eps * v, b, m2) - expect) / expect,
+    }
+
+
+@pytest.mark.parametrize("dims,m2", [((2, 2, 2, 2), 0.1), ((3, 2, 4, 2), 0.5)])
+def test_true_residual_checker(dims, m2):
+    errs = residual_checker_errors(dims, m2)
+    assert errs["scaled"] < 1e-13, errs
+    assert errs["zero"] < 1e-14, errs
+    assert errs["perturbed"] < 1e-6, errs
+
+
 # ------------------------------------------------------- planted mistakes
 
 def _mutated_laplace(kind):
@@ -299,3 +326,20 @@ def test_cg_mutation_detected(kind):
         except (ZeroDivisionError, FloatingPointError):
             e2 = np.inf
     assert not (e1 <= THRESH) or not (e2 <= 1e-10), (e1, e2)
+
+
+def _mutated_checker(kind):
+    def true_relative_residual(U, x, b, m2):
+        Lx = lap.laplace(U, x, 0.0 if kind == "m2_dropped" else m2)
+        r = b + Lx if kind == "sign" else b - Lx
+        r2 = np.vdot(r, r).real
+        den2 = np.vdot(x, x).real if kind == "normalised_by_x" else np.vdot(b, b).real
+        return float(r2 / den2) if kind == "no_sqrt" else float(np.sqrt(r2 / den2))
+    return true_relative_residual
+
+
+@pytest.mark.parametrize("kind", ["no_sqrt", "sign", "normalised_by_x", "m2_dropped"])
+def test_true_residual_mutation_detected(kind):
+    with np.errstate(all="ignore"):
+        errs = residual_checker_errors((2, 2, 2, 2), 0.1, checker=_mutated_checker(kind))
+    assert any(not (e <= 1e-6) for e in errs.values()), errs

@@ -190,3 +190,31 @@ def test_force_mutation_is_detected(kind, monkeypatch):
     _, worst_rel = pins.force_fd_errors((2, 2, 2, 2), 0.1, nentries=8)
     cov = pins.force_gauge_covariance_error((2, 2, 2, 4), 0.1)
     assert _detected({"fd": worst_rel, "cov": cov}, 1e-6)
+
+
+def _mutated_true_residual(kind):
+    def true_relative_residual(U, x, b, mass, rhs="source"):
+        if rhs == "source":
+            bp = dirac.wilson_D(U, b, mass) if kind == "bprime_without_dagger" else dirac.wilson_Ddag(U, b, mass)
+            if kind == "b_instead_of_bprime":
+                bp = b
+        else:
+            bp = b
+        Ax = dirac.wilson_D(U, x, mass) if kind == "D_instead_of_normal" else dirac.normal_op(U, x, mass)
+        r2 = float(np.vdot(bp - Ax, bp - Ax).real)
+        den2 = float(np.vdot(b, b).real) if kind == "normalised_by_b" else float(np.vdot(bp, bp).real)
+        if kind == "no_sqrt":
+            return r2 / den2
+        return float(np.sqrt(r2) / np.sqrt(den2))
+    return true_relative_residual
+
+
+@pytest.mark.parametrize("kind", ["no_sqrt", "normalised_by_b", "b_instead_of_bprime", "bprime_without_dagger",
+                                  "D_instead_of_normal"])
+def test_true_residual_mutation_is_detected(kind, monkeypatch):
+    monkeypatch.setattr(oracle, "true_relative_residual", _mutated_true_residual(kind))
+    errs = {}
+    for rhs in ("source", "normal"):
+        e = pins.residual_checker_errors((2, 2, 2, 2), 0.1, rhs=rhs)
+        errs.update({f"{rhs}_{k}": v for k, v in e.items()})
+    assert _detected(errs, 1e-6), errs

@@ -180,6 +180,23 @@ def test_cgnr_normal_rhs_mode():
     assert pins.rel(x, xd) < 1e-9
 
 
+@pytest.mark.parametrize("rhs", ["source", "normal"])
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (3, 2, 4, 2)])
+def test_true_residual_checker(dims, rhs):
+    # the checker every CG parity test relies on: |1 - c| for c x_d, 1 for
+    # x = 0, eps ||D^+D v|| / ||b'|| (dense) for x_d + eps v
+    errs = pins.residual_checker_errors(dims, 0.1, rhs=rhs)
+    assert errs["scaled"] < 1e-12, errs
+    assert errs["zero"] < 1e-14, errs
+    assert errs["perturbed"] < 1e-6, errs
+
+
+def test_true_residual_checker_other_scale():
+    # a second scale factor, above 1 (residual -(c - 1) b')
+    errs = pins.residual_checker_errors((2, 2, 2, 2), 0.3, c=1.75, seed=31)
+    assert errs["scaled"] < 1e-12, errs
+
+
 # ------------------------------------------------------------- force
 
 def test_force_matches_central_fd_2x2x2x2():
