@@ -188,6 +188,30 @@ int cg_solve(const wd_lattice* lat, double mass, const void* U, const void* b, v
              const wd_cg_params* params, wd_cg_result* result, void* workspace, size_t ws_bytes, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): cg_solve
+ * with its workspace taken from a static device array of 256 MiB that the
+ * library holds on every device it runs on, from its load to the end of the
+ * process, instead of a caller-owned buffer. Arguments, results, return codes
+ * and blocking behaviour as cg_solve; the caller still owns U, b and x. The
+ * call itself allocates nothing: no hipMalloc / hipFree, no pinned host
+ * buffers and no events (the device state is polled by synchronous copies
+ * into host memory), so params->profile must be 0 (else WD_ERR_INVALID).
+ * A solve whose single-system workspace (the layout cg_solve would carve; at
+ * most wd_workspace_bytes(lat, params, 1)) exceeds 256 MiB is rejected with
+ * WD_ERR_WORKSPACE before anything is launched: e.g. FP64 CG fits lattices
+ * up to about 16^3 x 32; a mixed solve's ring of search directions may need
+ * a smaller params->ring_len. Every call on a device shares that device's
+ * array and leaves its contents behind; nothing in it needs to start at zero
+ * (each solve initialises its state). Calls on one device are serialised
+ * with cg_solve's (one device mutex) and each returns after its device work
+ * has finished, so calls from several host threads do not overlap; work
+ * that a caller enqueues on the array by other means would race with them.
+ */
+int cg_solve_noalloc(const wd_lattice* lat, double mass, const void* U, const void* b, void* x,
+                     const wd_cg_params* params, wd_cg_result* result, void* stream);
+
+/*
  * Solve nrhs systems sharing one gauge field (the batched multi-RHS form of
  * the mixed-precision CG, Sec. 2 and Sec. 3.2 applied per system).
  * B, X: device, (nrhs, Lt, Lz, Ly, Lx, 4, 3) of element type params->io_dtype.

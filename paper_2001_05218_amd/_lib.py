@@ -83,6 +83,7 @@ SIGNATURES = {
     "wilson_apply_dagger": (ctypes.c_int, [_LAT, ctypes.c_double, _P, _P, _P, _P]),
     "wd_workspace_bytes": (ctypes.c_size_t, [_LAT, _PAR, ctypes.c_int32]),
     "cg_solve": (ctypes.c_int, [_LAT, ctypes.c_double, _P, _P, _P, _PAR, _RES, _P, ctypes.c_size_t, _P]),
+    "cg_solve_noalloc": (ctypes.c_int, [_LAT, ctypes.c_double, _P, _P, _P, _PAR, _RES, _P]),
     "cg_solve_batched": (ctypes.c_int, [_LAT, ctypes.c_double, _P, ctypes.c_int32, _P, _P, _PAR, _RES, _P,
                                         ctypes.c_size_t, _P]),
     "wilson_force": (ctypes.c_int, [_LAT, _P, _P, ctypes.c_double, ctypes.c_int32, _P, _P]),

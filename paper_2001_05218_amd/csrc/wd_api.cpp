@@ -563,13 +563,22 @@ namespace {
 
 // Polls device state between chunks of enqueued iterations. Two chunks are
 // in flight: while the host waits for chunk k, chunk k + 1 is already queued.
+// Without a pinned mirror (m == nullptr: the allocation-free solve) a wait
+// synchronises the stream and copies the state into host memory directly, so
+// it sees the state after every chunk posted so far.
 struct Poller {
   HostMirror* m;
   SolverState* dst;
   hipStream_t s;
   int slot = 0;
   int pending = 0;
+  SolverState* src = nullptr;
   int post(SolverState* st) {
+    if (!m) {
+      src = st;
+      ++pending;
+      return WD_OK;
+    }
     HIP_TRY(hipMemcpyAsync(m->buf[slot], st, sizeof(SolverState), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipEventRecord(m->ev[slot], s));
     slot ^= 1;
@@ -578,6 +587,12 @@ struct Poller {
   }
   // Wait for the oldest posted copy.
   int wait(SolverState* out) {
+    if (!m) {
+      HIP_TRY(hipMemcpyAsync(out, src, sizeof(SolverState), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      --pending;
+      return WD_OK;
+    }
     const int k = pending == 2 ? slot : slot ^ 1;
     HIP_TRY(hipEventSynchronize(m->ev[k]));
     *out = *m->buf[k];
@@ -592,6 +607,20 @@ struct Poller {
     return WD_OK;
   }
 };
+
+// The device state, now (stream synchronised), through the pinned mirror or,
+// without one, straight into host memory.
+int read_state(HostMirror* m, const SolverState* st, hipStream_t s, SolverState* out) {
+  if (!m) {
+    HIP_TRY(hipMemcpyAsync(out, st, sizeof(SolverState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return WD_OK;
+  }
+  HIP_TRY(hipMemcpyAsync(m->buf[0], st, sizeof(SolverState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *out = *m->buf[0];
+  return WD_OK;
+}
 
 // Iterations to enqueue next, from the observed convergence rate.
 int next_chunk(const SolverState& s, int enqueued, int max_iter) {
@@ -646,15 +675,17 @@ int cg_setup(const Geom& g, double mass, const void* U, const void* b, void* x, 
   return WD_OK;
 }
 
+// noalloc: no pinned mirror and no timing events (cg_solve_noalloc).
 int cg_plain(const Geom& g, double mass, const void* U, const void* b, void* x, const wd_cg_params* p,
-             wd_cg_result* res, void* ws, hipStream_t s, std::chrono::steady_clock::time_point t0) {
+             wd_cg_result* res, void* ws, hipStream_t s, std::chrono::steady_clock::time_point t0,
+             bool noalloc = false) {
   const CgWorkspace w = layout_cg(ws, g, WD_F64, p->history_len, ring_length(p, g));
   int rc = cg_setup(g, mass, U, b, x, p, w, 0, 0.0, w.r64, s);
   if (rc) return rc;
   launch_convert(g, w.r64, w.p64, G_ALWAYS, w.st, s);
 
-  HostMirror* m;
-  if ((rc = get_mirror(&m))) return rc;
+  HostMirror* m = nullptr;
+  if (!noalloc && (rc = get_mirror(&m))) return rc;
   KernelClock* clk = nullptr;
   if (p->profile && (rc = get_clock(&clk))) return rc;
   Poller poll{m, nullptr, s};
@@ -727,7 +758,8 @@ int cg_plain(const Geom& g, double mass, const void* U, const void* b, void* x, 
 // low-precision fields; the solution accumulates in FP32 between updates and
 // is flushed into FP64 x, where the residual is recomputed exactly.
 int cg_mixed(const Geom& g, double mass, const void* U, const void* b, void* x, const wd_cg_params* p,
-             wd_cg_result* res, void* ws, hipStream_t s, std::chrono::steady_clock::time_point t0) {
+             wd_cg_result* res, void* ws, hipStream_t s, std::chrono::steady_clock::time_point t0,
+             bool noalloc = false) {
   const int P = p->inner_prec;
   const bool refine = p->scheme == WD_ITERATIVE_REFINEMENT;
   // refinement: no periodic recomputation, only after each inner solve
@@ -737,16 +769,16 @@ int cg_mixed(const Geom& g, double mass, const void* U, const void* b, void* x, 
   int rc = cg_setup(g, mass, U, b, x, p, w, interval, delta, w.rh, s);
   if (refine) launch_set_restart(w.st, s);
   if (rc) return rc;
-  HostMirror* m;
-  if ((rc = get_mirror(&m))) return rc;
+  HostMirror* m = nullptr;
+  if (!noalloc && (rc = get_mirror(&m))) return rc;
   // 16-bit inner links: two rows per link (row 2 rebuilt from unitarity) when
   // every link is SU(3) to 1e-9; the full 9 entries otherwise.
   int rows2 = 0;
   if (narrow_prec(P) && g.tiled) {
     launch_su3_check(g, U, w.st, w.partials, s);
-    HIP_TRY(hipMemcpyAsync(m->buf[0], w.st, sizeof(SolverState), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    rows2 = m->buf[0]->su3_dev <= 1e-9;
+    SolverState chk;
+    if ((rc = read_state(m, w.st, s, &chk))) return rc;
+    rows2 = chk.su3_dev <= 1e-9;
   }
   if (rows2) launch_pack_gauge_rows2(g, U, P, w.Ulow, s);
   else launch_pack_gauge(g, U, P, w.Ulow, s);
@@ -1188,4 +1220,62 @@ extern "C" int cg_solve_batched(const wd_lattice* lat, double mass, const void* 
   rc = batched_solve(g, mass, U, nrhs, B, X, params, results, workspace, as_stream(stream), err, sizeof(err));
   if (rc != WD_OK) return fail(rc, "%s", err);
   return WD_OK;
+}
+
+// ---- allocation-free solve: cg_solve with the workspace in a static device
+// array instead of a caller-owned buffer, for callers that cannot allocate
+// (HIP graph capture, serving loops). Each device the library runs on holds
+// its own copy of the array, from the library's load to the process's end.
+constexpr size_t kScratchBytes = size_t(256) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+// Device address of `scratch` per device (the name itself is a host-side
+// stand-in), looked up once per device with that device current.
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+int scratch_ptr(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(WD_ERR_HIP, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(WD_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return WD_OK;
+}
+
+}  // namespace
+
+extern "C" int cg_solve_noalloc(const wd_lattice* lat, double mass, const void* U, const void* b, void* x,
+                                const wd_cg_params* params, wd_cg_result* result, void* stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (result) std::memset(result, 0, sizeof(*result));
+  int rc = check_lattice(lat);
+  if (rc) return rc;
+  if ((rc = validate_params(params))) return rc;
+  if (params->profile) return fail(WD_ERR_INVALID, "cg_solve_noalloc: profile needs timing events (use cg_solve)");
+  if (!U || !b || !x) return fail(WD_ERR_INVALID, "NULL field pointer");
+  if (b == x) return fail(WD_ERR_INVALID, "b and x must not alias");
+  if (!std::isfinite(mass)) return fail(WD_ERR_INVALID, "mass is not finite");
+  const Geom g = packed_geom(lat);
+  const size_t need = layout_cg(nullptr, g, params->inner_prec, params->history_len, ring_length(params, g)).bytes;
+  if (need > kScratchBytes)
+    return fail(WD_ERR_WORKSPACE,
+                "cg_solve_noalloc: this solve needs %zu bytes of workspace, the static scratch holds %zu "
+                "(use cg_solve with a caller-owned workspace, or a smaller ring_len)",
+                need, kScratchBytes);
+  void* ws = nullptr;
+  if ((rc = scratch_ptr(&ws))) return rc;
+  const hipStream_t s = as_stream(stream);
+  std::unique_lock<std::mutex> lk;
+  if ((rc = lock_device(lk))) return rc;
+  if (params->inner_prec == WD_F64) return cg_plain(g, mass, U, b, x, params, result, ws, s, t0, true);
+  return cg_mixed(g, mass, U, b, x, params, result, ws, s, t0, true);
 }
