@@ -127,9 +127,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-other-rows", action="store_true",
                     help="skip the force, batched, autograd and Laplacian measurements")
-    ap.add_argument("--other-rows", default="force,batched,autograd,laplace",
+    ap.add_argument("--other-rows", default="force,batched,autograd,laplace,ooc",
                     help="comma-separated subset of the other rows to measure")
     ap.add_argument("--cpu-sample-only", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-plan", action="store_true",
+                    help="time the FP64 oracle on the host (per D and per CG iteration on the five workloads, full "
+                         "solves on the three small ones) and print one JSON line; no GPU is used")
+    ap.add_argument("--cpu-plan-part", default=None, help=argparse.SUPPRESS)
     return ap.parse_args()
 
 
@@ -177,6 +181,74 @@ def run_cpu_baseline(dims, fp64_iters):
                    f"value = that time x the {fp64_iters} iterations of the FP64 solve"),
         "iter_seconds": it,
     }
+
+
+# The five workloads (lattice (x, y, z, t), links, mass, link seed); sources are
+# Gaussian with seed + 1 (the batched one's first Gaussian source stands for its set).
+WORKLOADS = {
+    "c0_4x4x4x4": ((4, 4, 4, 4), "haar", 0.1, 200105218),
+    "c1_16x16x16x32": ((16, 16, 16, 32), "near_identity", 0.05, 200105228),
+    "c2_32x32x32x64": ((32, 32, 32, 64), "near_identity", 0.02, 200105238),
+    "c3_24x24x24x48": ((24, 24, 24, 48), "haar", 0.05, 200105248),
+    "c4_16x16x16x32": ((16, 16, 16, 32), "near_identity", 0.1, 200105258),
+}
+FULL_SOLVES = ("c0_4x4x4x4", "c1_16x16x16x32", "c4_16x16x16x32")
+
+
+def cpu_plan_part(name, full):
+    """Oracle timings of one workload in this (single-threaded) process."""
+    import fieldgen
+    import oracle
+    dims, kind, mass, seed = WORKLOADS[name]
+    U = fieldgen.gauge_field(dims, kind, seed, eps=EPS)
+    b = fieldgen.gaussian_spinor(dims, seed + 1)
+    t = time.perf_counter()
+    d = oracle.wilson_D(U, b, mass)
+    t_d = time.perf_counter() - t
+    # one CGNR iteration: D, D^+ and the vector updates
+    r = oracle.wilson_Ddag(U, b, mass)
+    p = r.copy()
+    x = np.zeros_like(b)
+    rho = float(np.vdot(r, r).real)
+    t = time.perf_counter()
+    tt = oracle.wilson_D(U, p, mass)
+    alpha = rho / float(np.vdot(tt, tt).real)
+    x += alpha * p
+    r -= alpha * oracle.wilson_Ddag(U, tt, mass)
+    rho2 = float(np.vdot(r, r).real)
+    p = r + (rho2 / rho) * p
+    t_it = time.perf_counter() - t
+    out = {"lattice_xyzt": list(dims), "sites": int(np.prod(dims)), "D_seconds": t_d, "iteration_seconds": t_it}
+    del d, tt, r, p, x
+    if full:
+        log(f"{name}: full oracle solve")
+        t = time.perf_counter()
+        _, info = oracle.cgnr(U, b, mass, tol=TOL, max_iter=20000)
+        out.update({"solve_seconds": time.perf_counter() - t, "iterations": info["iterations"],
+                    "true_rel_res": info["true_rel_res"]})
+    print(json.dumps({name: out}), flush=True)
+
+
+def run_cpu_plan():
+    """Every workload's timings in its own single-threaded child process; the
+    three full solves run side by side (one core each)."""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
+               HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
+    procs = {}
+    for name in WORKLOADS:
+        cmd = [sys.executable, os.path.abspath(__file__), "--cpu-plan-part", name]
+        procs[name] = subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env)
+        if name not in FULL_SOLVES:   # the large ones alone, so that they do not share memory bandwidth
+            procs[name].wait()
+    res = {}
+    for name, pr in procs.items():
+        outp, errp = pr.communicate()
+        if pr.returncode != 0:
+            raise RuntimeError(errp[-2000:])
+        res.update(json.loads(outp.strip().splitlines()[-1]))
+    print(json.dumps({"cpu_oracle_plan": res, "cores_per_run": 1, "host_logical_cpus": os.cpu_count(),
+                      "threads_env": {k: env[k] for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS",
+                                                         "MKL_NUM_THREADS")}}))
 
 
 # -------------------------------------------------------------------- GPU
@@ -342,11 +414,125 @@ def bench_laplace(dev, Ut):
     return out
 
 
+def stream_ceiling(dev, gib=8, reps=5):
+    """The library's plain streaming kernels (copy, read, write) over `gib` GiB
+    buffers, far beyond the 256 MiB Infinity Cache: what HBM delivers to a
+    perfectly coalesced stream."""
+    import ctypes
+    import torch
+    import paper_2001_05218_amd as wd
+    lib = wd._lib.load()
+    n = gib << 30
+    src = torch.ones(n, dtype=torch.uint8, device=dev)
+    dst = torch.empty(n, dtype=torch.uint8, device=dev)
+    part = torch.empty(int(lib.wd_stream_partials(n)) * 16, dtype=torch.uint8, device=dev)
+    s = torch.cuda.current_stream(dev)
+    out = {"buffer_GiB": gib}
+    for kind, name, mult in ((0, "copy", 2), (1, "read", 1), (2, "write", 1)):
+        d = part if kind == 1 else dst
+        for _ in range(2):
+            wd._lib.check(lib.wd_stream(kind, src.data_ptr(), d.data_ptr(), n, ctypes.c_void_p(s.cuda_stream)),
+                          "wd_stream")
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            lib.wd_stream(kind, src.data_ptr(), d.data_ptr(), n, ctypes.c_void_p(s.cuda_stream))
+        e1.record(s)
+        e1.synchronize()
+        out[f"{name}_GB_per_s"] = mult * n / (e0.elapsed_time(e1) / 1e3 / reps) / 1e9
+    del src, dst, part
+    torch.cuda.empty_cache()
+    return out
+
+
+def ooc_pcie_bytes(dims, ts, nslab, iters):
+    """Bytes one out-of-core solve moves each way: per slab k of t_k planes, an
+    iteration copies in the links of t_k + 1 planes twice (t = D p; D^+ t) and
+    t_k + 2, t_k + 2 + 3 t_k and 2 t_k spinor planes; it copies out t_k, 2 t_k
+    and t_k planes (t; x, r; p). Set-up (D^+ b; r = p = b'; x = 0) and the
+    final residual (D x; b' - D^+ t) are added once."""
+    lx, ly, lz, lt = dims
+    plane = lx * ly * lz
+    sp, lk = 192 * plane, 4 * 144 * plane
+    h2d = d2h = 0
+    for k in range(nslab):
+        t = min(ts, lt - k * ts)
+        h2d += iters * (2 * (t + 1) * lk + (t + 2 + t + 2 + 3 * t + 2 * t) * sp)
+        d2h += iters * (t + 2 * t + t) * sp
+        h2d += (t + 1) * lk + (t + 2) * sp + (t + 1) * lk + (t + 2) * sp + (t + 1) * lk + (t + 2 + t) * sp
+        d2h += 4 * t * sp + t * sp + 2 * t * sp
+    return h2d, d2h
+
+
+def bench_ooc(dev, budget=64 << 20):
+    """FP64 CG on 16^3x32 (links exp(i 0.3 H), m = 0.05) with U, b, x and the CG
+    vectors in pinned host memory and a 64 MiB device budget, against the same
+    solve resident in HBM and against the host link's copy rates."""
+    import torch
+    import fieldgen
+    import paper_2001_05218_amd as wd
+    dims, mass = (16, 16, 16, 32), 0.05
+    Uh = torch.from_numpy(fieldgen.gauge_field(dims, "near_identity", 200105228, eps=EPS)).pin_memory()
+    bh = torch.from_numpy(fieldgen.gaussian_spinor(dims, 200105229)).pin_memory()
+    dws = torch.empty(budget, dtype=torch.uint8, device=dev)
+    _, hb = wd.ooc_workspace_bytes(dims, 1)
+    hws = torch.empty(hb, dtype=torch.uint8, pin_memory=True)
+    wd.cg_solve_ooc(Uh, bh, mass, tol=TOL, max_iter=5000, device_workspace=dws, host_workspace=hws)
+    times = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x, info = wd.cg_solve_ooc(Uh, bh, mass, tol=TOL, max_iter=5000, device_workspace=dws, host_workspace=hws)
+        times.append(time.perf_counter() - t)
+    sec = min(times)
+    ts, ns, it = info["ooc_slab_planes"], info["ooc_slabs"], info["iterations"]
+    h2d, d2h = ooc_pcie_bytes(dims, ts, ns, it)
+    # the host link's rates for 1 GiB pinned copies, each direction alone
+    rates = {}
+    hbuf = torch.empty(1 << 30, dtype=torch.uint8, pin_memory=True)
+    dbuf = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    for name, f in (("H2D", lambda: dbuf.copy_(hbuf, non_blocking=True)),
+                    ("D2H", lambda: hbuf.copy_(dbuf, non_blocking=True))):
+        f()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(3):
+            f()
+        torch.cuda.synchronize()
+        rates[name] = 3 * (1 << 30) / (time.perf_counter() - t) / 1e9
+    del hbuf, dbuf
+    # the same solve with everything in HBM
+    Ud, bd = Uh.to(dev), bh.to(dev)
+    wd.cg_solve(Ud, bd, mass, tol=TOL, max_iter=5000)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, ih = wd.cg_solve(Ud, bd, mass, tol=TOL, max_iter=5000)
+    torch.cuda.synchronize()
+    t_hbm = time.perf_counter() - t
+    link_bound = max(h2d / (rates["H2D"] * 1e9), d2h / (rates["D2H"] * 1e9))
+    out = {"lattice_xyzt": list(dims), "mass": mass, "device_budget_bytes": budget, "slab_planes": ts,
+           "slabs": ns, "iterations": it, "true_rel_res": info["true_rel_res"], "seconds": sec,
+           "h2d_bytes": h2d, "d2h_bytes": d2h, "h2d_GB_per_s": h2d / sec / 1e9,
+           "link_rates_GB_per_s": rates, "link_bound_seconds": link_bound,
+           "overlap_efficiency": link_bound / sec, "in_hbm_seconds": t_hbm, "in_hbm_iterations": ih["iterations"],
+           "note": "overlap_efficiency = time the copies alone need at the measured pinned copy rates / solve time"}
+    del Ud, bd, dws, hws, Uh, bh, x
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     dims = tuple(int(v) for v in args.dims.split(","))
     if args.cpu_sample_only:
         cpu_sample(dims)
+        return
+    if args.cpu_plan_part:
+        cpu_plan_part(args.cpu_plan_part, args.cpu_plan_part in FULL_SOLVES)
+        return
+    if args.cpu_plan:
+        run_cpu_plan()
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the solver is a single-GPU "
@@ -423,6 +609,26 @@ def main():
     assert all(i["true_rel_res"] <= TOL for i in infos), infos
     log(f"mixed {best}: {per:.4f} s per solve")
 
+    # the 32^3x64 workload's own storages (BF16 and FP16 spinors and links),
+    # each timed over the same number of solves
+    config2 = {}
+    for inner in ("f16", "bf16"):
+        if inner not in ws:
+            continue
+        solve(inner, ws[inner])
+        torch.cuda.synchronize()
+        t_c = time.perf_counter()
+        for _ in range(args.steps):
+            _, ic = wd.cg_solve(Ut, bt, MASS, tol=TOL, max_iter=20000, inner=inner, reliable_interval=50,
+                                workspace=ws[inner])
+        torch.cuda.synchronize()
+        config2[inner] = {"seconds": (time.perf_counter() - t_c) / args.steps, "steps": args.steps,
+                          "iterations": ic["iterations"], "reliable_updates": ic["reliable_updates"],
+                          "true_rel_res": ic["true_rel_res"], "two_row_links": bool(ic["two_row_links"])}
+        assert ic["true_rel_res"] <= TOL
+    c2best = min(config2, key=lambda k: config2[k]["seconds"]) if config2 else None
+    log(f"config-2 storages: {config2}")
+
     # the other two-precision scheme, for comparison (outside the timed region)
     torch.cuda.synchronize()
     t_ir = time.perf_counter()
@@ -468,7 +674,11 @@ def main():
     torch.cuda.synchronize()
     log(f"dslash: {dsl}")
 
-    # practical ceiling and counter calibration: a plain 512 MiB device copy
+    # practical ceiling: the library's streaming kernels over 8 GiB buffers
+    ceiling = stream_ceiling(dev)
+    log(f"stream ceiling: {ceiling}")
+
+    # counter calibration: a plain 512 MiB device copy
     n = 512 * (1 << 20) // 4
     src = torch.ones(n, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
@@ -496,6 +706,8 @@ def main():
             other["autograd_solve"] = bench_autograd(dev)
         if "laplace" in rows:
             other["laplace_cg_32x32x32x64"] = bench_laplace(dev, Ut)
+        if "ooc" in rows:
+            other["out_of_core_cg_16x16x16x32"] = bench_ooc(dev)
         log(f"other rows: {other}")
 
     cpu = None
@@ -543,6 +755,11 @@ def main():
                      "rel_diff_vs_fp64_solution": diff},
         "fp64_cg": fp64,
         "refinement_cg": refinement,
+        "config2_storages": {"note": "BF16 and FP16 storage named by the 32^3x64 mixed-precision workload, each "
+                                     "timed over the same number of solves as the headline",
+                             "fastest": c2best, "speedup_vs_fp64": (fp64["seconds"] / config2[c2best]["seconds"]
+                                                                     if c2best else None),
+                             **config2},
         "speedup_mixed_vs_fp64": fp64["seconds"] / per,
         # inner-loop stencils only (two per CG iteration, 1368 flop per site each)
         "stencil_TFLOP_per_s": {
@@ -553,6 +770,8 @@ def main():
         "dslash": dsl,
         "roofline": {"bound": "hbm", "kernel": kern["kernel"], "achieved": kern["GB_per_s"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kern["frac_hbm"],
+                     "stream_ceiling_GB_per_s": ceiling["copy_GB_per_s"],
+                     "frac_of_stream_ceiling": kern["GB_per_s"] / ceiling["copy_GB_per_s"],
                      "traffic": traffic["bytes"] if traffic else None,
                      "algorithmic_bytes": kern["bytes_per_site"] * V,
                      "avg_launch_us": kern["avg_us"],
@@ -560,6 +779,7 @@ def main():
         "loop_kernels": loop,
         "other_rows": other,
         "copy_ceiling_GB_per_s": copy_gbs,
+        "stream_ceiling": ceiling,
         "kernel_source_sha": kernel_source_sha(),
         "cpu_baseline": cpu,
     }

@@ -143,6 +143,8 @@ typedef struct {
   double kernel_seconds[3];  /* with params->profile: average device time of one launch of the inner
                                 loop's (0) t = D p kernel, (1) fused D^+ t / r update kernel (plain
                                 FP64 CG: also x += alpha p), (2) p = r + beta p kernel; 0 otherwise */
+  int32_t ooc_slab_planes;   /* cg_solve_ooc: time planes per slab of its schedule; 0 otherwise */
+  int32_t ooc_slabs;         /* cg_solve_ooc: slabs per sweep; 0 otherwise */
 } wd_cg_result;
 
 /* Thread-local text of the last non-zero return on the calling thread. */
@@ -253,6 +255,60 @@ int cg_solve_batched(const wd_lattice* lat, double mass, const void* U, int32_t 
  */
 int wilson_force(const wd_lattice* lat, const void* a, const void* b, double coeff, int32_t accumulate, void* F,
                  void* stream);
+
+/* ---- out-of-core solve: fields larger than (or kept out of) device memory ----
+ *
+ * The paper's accelerator computes on the first complete inputs while later
+ * data is still streaming in over the host link, which removes the limit that
+ * local memory would put on the problem size (Sec. 2, Sec. 3.1, Sec. 4 and
+ * Fig. 2). cg_solve_ooc runs the plain FP64 CG of cg_solve with the gauge
+ * field, b, x and the CG vectors in HOST memory: each operator application
+ * streams the lattice through the GPU in slabs of whole time planes (each slab
+ * with one halo plane on either side, periodic in t), on three HIP streams
+ * (copies in, kernels, copies out) and two device buffer sets, so that copies
+ * of neighbouring slabs overlap the kernels. One iteration moves about
+ * 2.5 KB per site to the device and 0.8 KB back. */
+
+/* Workspace of cg_solve_ooc for slabs of slab_planes time planes
+ * (1 <= slab_planes <= Lt) and a residual history of history_len entries:
+ * *device_bytes (device memory) and *host_bytes (pinned host memory: four
+ * FP64 spinor fields, b' r p t). Either pointer may be NULL. Returns WD_OK or
+ * WD_ERR_INVALID. */
+int wd_ooc_workspace_bytes(const wd_lattice* lat, int32_t slab_planes, int32_t history_len, size_t* device_bytes,
+                           size_t* host_bytes);
+
+/*
+ * Out-of-core D^+ D x = D^+ b (or b) by plain FP64 CG.
+ *   U, b, x          PINNED HOST memory (hipHostMalloc, or a pinned torch tensor),
+ *                    canonical complex128 layouts; x: initial guess unless
+ *                    params->zero_guess, solution on return
+ *   host_workspace   pinned host memory, >= host_bytes of wd_ooc_workspace_bytes
+ *   device_workspace device memory of device_ws_bytes: the device budget. The
+ *                    solve uses the thickest slabs (at most about Lt / 4 planes,
+ *                    so that there are slabs to overlap) whose buffers fit;
+ *                    WD_ERR_WORKSPACE if not even one-plane slabs fit.
+ * params: tol, max_iter, rhs_mode, zero_guess, history / history_len as for
+ * cg_solve; inner_prec must be WD_F64, io_dtype WD_C128, profile 0 (else
+ * WD_ERR_INVALID). result->ooc_slab_planes / ooc_slabs report the schedule.
+ * The solve starts after the work already queued on `stream` and BLOCKS until
+ * it ends (it runs on the library's own streams). Returns WD_OK,
+ * WD_NOT_CONVERGED (x holds the last iterate), or a WD_ERR_* code (pageable
+ * host memory: WD_ERR_INVALID).
+ */
+int cg_solve_ooc(const wd_lattice* lat, double mass, const void* U, const void* b, void* x,
+                 const wd_cg_params* params, wd_cg_result* result, void* host_workspace, size_t host_ws_bytes,
+                 void* device_workspace, size_t device_ws_bytes, void* stream);
+
+/* ---- measurement: plain streaming kernels, the practical HBM ceiling ----
+ * The paper states that its stencil is limited only by memory bandwidth
+ * (Sec. 3.1.2); these kernels measure what a perfectly coalesced stream gets
+ * from HBM on this device, for comparison with the stencils. kind 0: dst = src
+ * (bytes read and bytes written); 1: read src, an XOR of all words per
+ * workgroup goes to dst (wd_stream_partials(bytes) 16-byte words); 2: dst = 0
+ * (bytes written). Device pointers, 16-byte aligned; bytes a multiple of 16.
+ * Asynchronous on `stream`. */
+int wd_stream(int32_t kind, const void* src, void* dst, size_t bytes, void* stream);
+size_t wd_stream_partials(size_t bytes);
 
 /* ---- packed fields: the solver's internal site-blocked layout, for callers that
  *      apply D repeatedly without repacking (and for timing the hot kernel). ---- */

@@ -10,6 +10,8 @@ from .ops import (  # noqa: F401
     wilson_force,
     cg_solve,
     cg_solve_batched,
+    cg_solve_ooc,
+    ooc_workspace_bytes,
     pack_gauge,
     pack_spinor,
     unpack_spinor,

@@ -62,6 +62,8 @@ class WdCgResult(ctypes.Structure):
         ("iter_rel_res", ctypes.c_double),
         ("seconds", ctypes.c_double),
         ("kernel_seconds", ctypes.c_double * 3),
+        ("ooc_slab_planes", ctypes.c_int32),
+        ("ooc_slabs", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -84,6 +86,12 @@ SIGNATURES = {
     "wd_workspace_bytes": (ctypes.c_size_t, [_LAT, _PAR, ctypes.c_int32]),
     "cg_solve": (ctypes.c_int, [_LAT, ctypes.c_double, _P, _P, _P, _PAR, _RES, _P, ctypes.c_size_t, _P]),
     "cg_solve_noalloc": (ctypes.c_int, [_LAT, ctypes.c_double, _P, _P, _P, _PAR, _RES, _P]),
+    "wd_ooc_workspace_bytes": (ctypes.c_int, [_LAT, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t),
+                                              ctypes.POINTER(ctypes.c_size_t)]),
+    "cg_solve_ooc": (ctypes.c_int, [_LAT, ctypes.c_double, _P, _P, _P, _PAR, _RES, _P, ctypes.c_size_t, _P,
+                                    ctypes.c_size_t, _P]),
+    "wd_stream": (ctypes.c_int, [ctypes.c_int32, _P, _P, ctypes.c_size_t, _P]),
+    "wd_stream_partials": (ctypes.c_size_t, [ctypes.c_size_t]),
     "cg_solve_batched": (ctypes.c_int, [_LAT, ctypes.c_double, _P, ctypes.c_int32, _P, _P, _PAR, _RES, _P,
                                         ctypes.c_size_t, _P]),
     "wilson_force": (ctypes.c_int, [_LAT, _P, _P, ctypes.c_double, ctypes.c_int32, _P, _P]),

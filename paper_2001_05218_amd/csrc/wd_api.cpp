@@ -1279,3 +1279,80 @@ extern "C" int cg_solve_noalloc(const wd_lattice* lat, double mass, const void* 
   if (params->inner_prec == WD_F64) return cg_plain(g, mass, U, b, x, params, result, ws, s, t0, true);
   return cg_mixed(g, mass, U, b, x, params, result, ws, s, t0, true);
 }
+
+// ---- out-of-core solve (wd_ooc.hip) and the streaming measurement kernels
+
+namespace {
+
+// Host memory the GPU can copy from asynchronously: pinned (page-locked) and
+// known to the HIP runtime.
+bool pinned_host(const void* p) {
+  hipPointerAttribute_t a{};
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();   // pageable memory: clear the error the query left
+    return false;
+  }
+  return a.type == hipMemoryTypeHost;
+}
+
+}  // namespace
+
+extern "C" int wd_ooc_workspace_bytes(const wd_lattice* lat, int32_t slab_planes, int32_t history_len,
+                                      size_t* device_bytes, size_t* host_bytes) {
+  int rc = check_lattice(lat);
+  if (rc) return rc;
+  if (slab_planes < 1 || slab_planes > lat->L[3])
+    return fail(WD_ERR_INVALID, "slab_planes = %d must be in [1, Lt = %d]", slab_planes, lat->L[3]);
+  if (history_len < 0) return fail(WD_ERR_INVALID, "history_len = %d", history_len);
+  if (device_bytes) *device_bytes = ooc_device_bytes(lat->L, slab_planes, history_len);
+  if (host_bytes) *host_bytes = ooc_host_bytes(lat->L);
+  return WD_OK;
+}
+
+extern "C" int cg_solve_ooc(const wd_lattice* lat, double mass, const void* U, const void* b, void* x,
+                            const wd_cg_params* params, wd_cg_result* result, void* host_workspace,
+                            size_t host_ws_bytes, void* device_workspace, size_t device_ws_bytes, void* stream) {
+  if (result) std::memset(result, 0, sizeof(*result));
+  int rc = check_lattice(lat);
+  if (rc) return rc;
+  if ((rc = validate_params(params))) return rc;
+  if (params->inner_prec != WD_F64) return fail(WD_ERR_INVALID, "cg_solve_ooc runs FP64 CG: inner_prec must be WD_F64");
+  if (params->io_dtype != WD_C128) return fail(WD_ERR_INVALID, "cg_solve_ooc takes complex128 fields (io_dtype WD_C128)");
+  if (params->profile) return fail(WD_ERR_INVALID, "cg_solve_ooc does not profile kernels (profile must be 0)");
+  if (!U || !b || !x || !host_workspace) return fail(WD_ERR_INVALID, "NULL field or host workspace pointer");
+  if (b == x) return fail(WD_ERR_INVALID, "b and x must not alias");
+  if (!std::isfinite(mass)) return fail(WD_ERR_INVALID, "mass is not finite");
+  const void* host_ptrs[4] = {U, b, x, host_workspace};
+  const char* names[4] = {"U", "b", "x", "host_workspace"};
+  for (int i = 0; i < 4; ++i)
+    if (!pinned_host(host_ptrs[i]))
+      return fail(WD_ERR_INVALID, "cg_solve_ooc: %s is not pinned host memory (hipHostMalloc or a pinned tensor)",
+                  names[i]);
+  const size_t host_need = ooc_host_bytes(lat->L);
+  if (host_ws_bytes < host_need)
+    return fail(WD_ERR_WORKSPACE, "host workspace of %zu bytes given, %zu needed", host_ws_bytes, host_need);
+  if (!device_workspace || ooc_slab_planes(lat->L, device_ws_bytes, params->history_len) < 1)
+    return fail(WD_ERR_WORKSPACE, "device workspace of %zu bytes is below the %zu of one-plane slabs",
+                device_workspace ? device_ws_bytes : 0, ooc_device_bytes(lat->L, 1, params->history_len));
+  std::unique_lock<std::mutex> lk;
+  if ((rc = lock_device(lk))) return rc;
+  char err[512] = {0};
+  rc = ooc_solve(lat->L, mass, U, b, x, params, result, host_workspace, device_workspace, device_ws_bytes,
+                 as_stream(stream), err, sizeof(err));
+  if (rc != WD_OK) return fail(rc, "%s", err);
+  return WD_OK;
+}
+
+extern "C" int wd_stream(int32_t kind, const void* src, void* dst, size_t bytes, void* stream) {
+  if (kind < 0 || kind > 2) return fail(WD_ERR_INVALID, "kind = %d unknown", kind);
+  if (bytes % 16) return fail(WD_ERR_INVALID, "bytes = %zu is not a multiple of 16", bytes);
+  if ((kind != 2 && !src) || !dst) return fail(WD_ERR_INVALID, "NULL pointer");
+  if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15)
+    return fail(WD_ERR_INVALID, "pointers must be 16-byte aligned");
+  if (bytes == 0) return WD_OK;
+  launch_stream(kind, src, dst, bytes, as_stream(stream));
+  HIP_TRY(hipGetLastError());
+  return WD_OK;
+}
+
+extern "C" size_t wd_stream_partials(size_t bytes) { return stream_read_partials(bytes); }

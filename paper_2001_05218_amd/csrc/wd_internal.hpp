@@ -201,6 +201,22 @@ void launch_lap_norm2(const Geom& g, const void* v, int fin, SolverState* st, do
 // dst = src, or dst = 0 when src is null (gated)
 void launch_lap_copy(const Geom& g, const void* src, void* dst, int gate, SolverState* st, hipStream_t s);
 
+// ---- out-of-core FP64 CG (wd_ooc.hip): host-resident fields streamed in t-slabs.
+// Device bytes for slabs of `slab_planes` time planes; host bytes of the CG vectors.
+size_t ooc_device_bytes(const int L[4], int slab_planes, int hist_len);
+size_t ooc_host_bytes(const int L[4]);
+// Thickest slab (planes) that fits `device_bytes`, at most about a quarter of Lt; 0 if none.
+int ooc_slab_planes(const int L[4], size_t device_bytes, int hist_len);
+// The solve after argument validation; writes a message to err on a non-zero return.
+int ooc_solve(const int L[4], double mass, const void* U, const void* b, void* x, const ::wd_cg_params* p,
+              ::wd_cg_result* res, void* host_ws, void* dev_ws, size_t dev_ws_bytes, hipStream_t caller, char* err,
+              size_t errlen);
+
+// ---- streaming kernels (wd_stream.hip): kind 0 copy, 1 read (XOR per workgroup
+// into dst), 2 write zeros; bytes a multiple of 16.
+void launch_stream(int kind, const void* src, void* dst, size_t bytes, hipStream_t s);
+unsigned stream_read_partials(size_t bytes);
+
 // G(a, b) force on canonical complex128 spinors -> canonical complex128 links.
 void launch_force(const Geom& g, const void* a, const void* b, double coeff, int accumulate, void* F, hipStream_t s);
 

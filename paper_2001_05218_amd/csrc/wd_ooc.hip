@@ -1,0 +1,659 @@
+// Out-of-core FP64 CG: the gauge field and every CG vector stay in pinned host
+// memory and stream through the GPU in slabs of time planes.
+//
+// The paper's accelerator starts on the first complete set of inputs while the
+// rest of the data is still arriving over the host link, which frees the
+// computation from the size of the accelerator's local memory (Sec. 2;
+// Sec. 3.1; Sec. 4 and Fig. 2, three input streams and one output stream).
+// Here the same holds per t-slab: a sweep walks the lattice slab by slab with
+// three HIP streams (host-to-device copies, kernels, device-to-host copies)
+// and two device buffer sets, so that while slab k is computed, slab k + 1 is
+// copied in and slab k - 1 copied out. The stencil needs the planes on both
+// sides of a slab; the window copied in holds them (a lower and an upper halo
+// plane, periodic in t), and the links of the plane below.
+//
+// One CGNR iteration is three sweeps (with b' = D^+ b or b, M = D^+ D):
+//   S1  t = D p              in: U, p window    out: t      ||t||^2 -> alpha
+//   S2  q = D^+ t; x += alpha p; r -= alpha q
+//                            in: U, t window, x, p, r      out: x, r     ||r||^2 -> beta
+//   S3  p = r + beta p       in: r, p           out: p
+// The scalars never leave the device (finalize kernels on the kernel stream);
+// the host reads the state once per iteration, after S3 has been queued.
+// Each sweep may start copying in as soon as the slabs it reads have been
+// written back by the sweep before: a sweep whose input is a window starts one
+// slab later than the sweep before it (its first slab then needs only slabs
+// that were written back first), so consecutive sweeps overlap instead of
+// draining the pipeline.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <mutex>
+#include <vector>
+
+#include "wd_dslash.hpp"
+#include "wd_internal.hpp"
+#include "wd_reduce.hpp"
+
+namespace wd {
+
+// ---------------------------------------------------------------- geometry
+
+// A window: `ts` slab planes plus one halo plane below (window plane 0) and
+// one above; sites numbered canonically within it (x fastest, plane-major).
+struct SlabGeom {
+  int L[3];      // Lx, Ly, Lz
+  int plane;     // Lx * Ly * Lz
+  int ts;        // planes of this slab
+  FastDiv dx, dy, dz;
+};
+
+__device__ __forceinline__ Nbrs slab_neighbours(const SlabGeom& g, int w) {
+  uint32_t q = fdiv((uint32_t)w, g.dx);
+  const int x = w - (int)q * g.L[0];
+  const uint32_t q2 = fdiv(q, g.dy);
+  const int y = (int)q - (int)q2 * g.L[1];
+  const uint32_t q3 = fdiv(q2, g.dz);
+  const int z = (int)q2 - (int)q3 * g.L[2];
+  const int c[3] = {x, y, z};
+  const int st[3] = {1, g.L[0], g.L[0] * g.L[1]};
+  Nbrs n;
+#pragma unroll
+  for (int mu = 0; mu < 3; ++mu) {
+    const int span = st[mu] * (g.L[mu] - 1);
+    n.fwd[mu] = (c[mu] == g.L[mu] - 1) ? w - span : w + st[mu];
+    n.bwd[mu] = (c[mu] == 0) ? w + span : w - st[mu];
+  }
+  n.fwd[3] = w + g.plane;   // the halo planes make t local
+  n.bwd[3] = w - g.plane;
+  return n;
+}
+
+// ------------------------------------------------------------------ kernels
+// Thread i works on slab site i (window site plane + i). Partial sums go to
+// partials[blockIdx.x] (the host offsets the pointer per slab).
+
+template <bool DAG>
+__global__ __launch_bounds__(kBlock) void k_ooc_apply(SlabGeom g, CanonGauge U, CanonSpinor in,
+                                                      double2* __restrict__ out, double diag,
+                                                      double* __restrict__ partials) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  double n2 = 0.0;
+  if (i < g.ts * g.plane) {
+    const int w = g.plane + i;
+    double o[24];
+    wilson_site<DAG>(U, in, w, slab_neighbours(g, w), diag, o);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      out[(size_t)i * 12 + k] = make_double2(o[2 * k], o[2 * k + 1]);
+      n2 += o[2 * k] * o[2 * k] + o[2 * k + 1] * o[2 * k + 1];
+    }
+  }
+  store_partial(n2, partials);
+}
+
+// q = D^+ t; x += alpha p; r -= alpha q; ||r||^2.
+__global__ __launch_bounds__(kBlock) void k_ooc_update(SlabGeom g, CanonGauge U, CanonSpinor t,
+                                                       double2* __restrict__ x, const double2* __restrict__ p,
+                                                       double2* __restrict__ r, double diag,
+                                                       const SolverState* __restrict__ st,
+                                                       double* __restrict__ partials) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  double n2 = 0.0;
+  if (i < g.ts * g.plane) {
+    const int w = g.plane + i;
+    double q[24];
+    wilson_site<true>(U, t, w, slab_neighbours(g, w), diag, q);
+    const double a = st->alpha;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const size_t e = (size_t)i * 12 + k;
+      const double2 pv = p[e];
+      double2 xv = x[e], rv = r[e];
+      xv.x = fma(a, pv.x, xv.x);
+      xv.y = fma(a, pv.y, xv.y);
+      rv.x = fma(-a, q[2 * k], rv.x);
+      rv.y = fma(-a, q[2 * k + 1], rv.y);
+      x[e] = xv;
+      r[e] = rv;
+      n2 += rv.x * rv.x + rv.y * rv.y;
+    }
+  }
+  store_partial(n2, partials);
+}
+
+// r = b' - D^+ t (and p = r when p is given); ||r||^2.
+__global__ __launch_bounds__(kBlock) void k_ooc_residual(SlabGeom g, CanonGauge U, CanonSpinor t,
+                                                         const double2* __restrict__ bp, double2* __restrict__ r,
+                                                         double2* __restrict__ p, double diag,
+                                                         double* __restrict__ partials) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  double n2 = 0.0;
+  if (i < g.ts * g.plane) {
+    const int w = g.plane + i;
+    double q[24];
+    wilson_site<true>(U, t, w, slab_neighbours(g, w), diag, q);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const size_t e = (size_t)i * 12 + k;
+      const double2 b = bp[e];
+      const double2 v = make_double2(b.x - q[2 * k], b.y - q[2 * k + 1]);
+      r[e] = v;
+      if (p) p[e] = v;
+      n2 += v.x * v.x + v.y * v.y;
+    }
+  }
+  store_partial(n2, partials);
+}
+
+// p = r + beta p over n complex numbers.
+__global__ __launch_bounds__(kBlock) void k_ooc_p_update(size_t n, const double2* __restrict__ r,
+                                                         double2* __restrict__ p,
+                                                         const SolverState* __restrict__ st) {
+  const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= n) return;
+  const double beta = st->beta;
+  const double2 rv = r[e];
+  double2 pv = p[e];
+  pv.x = fma(beta, pv.x, rv.x);
+  pv.y = fma(beta, pv.y, rv.y);
+  p[e] = pv;
+}
+
+// ||v||^2 of n sites.
+__global__ __launch_bounds__(kBlock) void k_ooc_norm2(int n, const double2* __restrict__ v,
+                                                      double* __restrict__ partials) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  double n2 = 0.0;
+  if (i < n) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const double2 a = v[(size_t)i * 12 + k];
+      n2 += a.x * a.x + a.y * a.y;
+    }
+  }
+  store_partial(n2, partials);
+}
+
+// ------------------------------------------------------------------ layout
+
+namespace {
+
+constexpr size_t kSpinorSite = 12 * sizeof(double2);   // 192 B
+constexpr size_t kLinkSite = 9 * sizeof(double2);      // 144 B per direction
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+struct OocSet {
+  double2* U;      // 4 x (ts + 1) planes of links (window planes 0 .. ts)
+  double2* win;    // ts + 2 planes of a spinor (window)
+  double2* s[3];   // ts planes each
+};
+
+struct OocLayout {
+  SolverState* st;
+  double* hist;
+  double* partials;   // nslab x bps
+  OocSet set[2];
+  size_t bytes;
+};
+
+int blocks_per_slab(int ts, int plane) { return (ts * plane + kBlock - 1) / kBlock; }
+
+OocLayout ooc_layout(void* base, int plane, int T, int ts, int hist_len) {
+  char* b = static_cast<char*>(base);
+  size_t off = 0;
+  auto take = [&](size_t n) -> void* {
+    void* p = b ? b + off : nullptr;
+    off += align256(n);
+    return p;
+  };
+  OocLayout L{};
+  const int nslab = (T + ts - 1) / ts;
+  L.st = static_cast<SolverState*>(take(sizeof(SolverState)));
+  L.hist = static_cast<double*>(take(sizeof(double) * (size_t)std::max(hist_len, 1)));
+  L.partials = static_cast<double*>(take(sizeof(double) * (size_t)nslab * blocks_per_slab(ts, plane)));
+  for (int j = 0; j < 2; ++j) {
+    L.set[j].U = static_cast<double2*>(take(4 * (size_t)(ts + 1) * plane * kLinkSite));
+    L.set[j].win = static_cast<double2*>(take((size_t)(ts + 2) * plane * kSpinorSite));
+    for (int k = 0; k < 3; ++k) L.set[j].s[k] = static_cast<double2*>(take((size_t)ts * plane * kSpinorSite));
+  }
+  L.bytes = off;
+  return L;
+}
+
+// Per-device streams and state mirror, created on first use (default
+// priority, non-blocking).
+struct OocDevice {
+  hipStream_t h2d = nullptr, comp = nullptr, d2h = nullptr;
+  SolverState* mirror = nullptr;   // pinned
+  hipEvent_t mirror_ev = nullptr;
+  bool ready = false;
+};
+std::mutex g_ooc_mu;
+OocDevice g_ooc[64];
+
+#define OOC_TRY(call)                                                                         \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) {                                                                   \
+      snprintf(err, errlen, "%s: %s", #call, hipGetErrorString(e_));                          \
+      return WD_ERR_HIP;                                                                      \
+    }                                                                                         \
+  } while (0)
+
+int ooc_device(OocDevice** out, char* err, size_t errlen) {
+  int dev = 0;
+  OOC_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) {
+    snprintf(err, errlen, "device index %d out of range", dev);
+    return WD_ERR_HIP;
+  }
+  std::lock_guard<std::mutex> lk(g_ooc_mu);
+  OocDevice& d = g_ooc[dev];
+  if (!d.ready) {
+    OOC_TRY(hipStreamCreateWithFlags(&d.h2d, hipStreamNonBlocking));
+    OOC_TRY(hipStreamCreateWithFlags(&d.comp, hipStreamNonBlocking));
+    OOC_TRY(hipStreamCreateWithFlags(&d.d2h, hipStreamNonBlocking));
+    OOC_TRY(hipHostMalloc(reinterpret_cast<void**>(&d.mirror), sizeof(SolverState), hipHostMallocDefault));
+    OOC_TRY(hipEventCreateWithFlags(&d.mirror_ev, hipEventDisableTiming));
+    d.ready = true;
+  }
+  *out = &d;
+  return WD_OK;
+}
+
+// The sweep machinery of one solve.
+struct Ooc {
+  // lattice
+  int T = 0, plane = 0, ts = 0, nslab = 0;
+  SlabGeom sg{};
+  double diag = 0.0;
+  // host fields (canonical complex128)
+  const double2* U = nullptr;   // (4, T, plane, 9)
+  const double2* b = nullptr;
+  double2* x = nullptr;
+  double2 *bp = nullptr, *r = nullptr, *p = nullptr, *t = nullptr;
+  // device
+  OocLayout L{};
+  OocDevice* dev = nullptr;
+  std::vector<hipEvent_t> out_ev;       // per slab: its latest write-back has finished
+  hipEvent_t in_ready[2]{}, comp_done[2]{}, set_free[2]{};
+  int start = 0;                        // first slab of the current sweep order
+  char* err = nullptr;
+  size_t errlen = 0;
+
+  int t0_of(int k) const { return k * ts; }
+  int ts_of(int k) const { return std::min(ts, T - k * ts); }
+  size_t sp_plane() const { return (size_t)plane * 12; }   // double2 per spinor plane
+  size_t u_plane() const { return (size_t)plane * 9; }     // double2 per link plane (one mu)
+  double* partials_of(int k) const { return L.partials + (size_t)k * blocks_per_slab(ts, plane); }
+  int total_partials() const { return nslab * blocks_per_slab(ts, plane); }
+
+  // planes [first, first + n) of a host spinor field (first may be -1 or T:
+  // periodic) into consecutive device planes
+  int copy_planes_in(double2* dst, const double2* src, int first, int n, hipStream_t s) {
+    int done = 0;
+    while (done < n) {
+      const int tp = ((first + done) % T + T) % T;
+      const int run = std::min(n - done, T - tp);
+      OOC_TRY(hipMemcpyAsync(dst + (size_t)done * sp_plane(), src + (size_t)tp * sp_plane(),
+                             (size_t)run * sp_plane() * sizeof(double2), hipMemcpyHostToDevice, s));
+      done += run;
+    }
+    return WD_OK;
+  }
+  int window_in(double2* dst, const double2* src, int k, hipStream_t s) {
+    return copy_planes_in(dst, src, t0_of(k) - 1, ts_of(k) + 2, s);
+  }
+  int slab_in(double2* dst, const double2* src, int k, hipStream_t s) {
+    OOC_TRY(hipMemcpyAsync(dst, src + (size_t)t0_of(k) * sp_plane(), (size_t)ts_of(k) * sp_plane() * sizeof(double2),
+                           hipMemcpyHostToDevice, s));
+    return WD_OK;
+  }
+  int slab_out(double2* dst, const double2* src, int k, hipStream_t s) {
+    OOC_TRY(hipMemcpyAsync(dst + (size_t)t0_of(k) * sp_plane(), src, (size_t)ts_of(k) * sp_plane() * sizeof(double2),
+                           hipMemcpyDeviceToHost, s));
+    return WD_OK;
+  }
+  // links of window planes 0 .. ts (lattice planes t0 - 1 .. t0 + ts - 1) for each mu;
+  // in the device window the directions are ts_max + 1 planes apart
+  int links_in(double2* dst, int k, hipStream_t s) {
+    const int n = ts_of(k) + 1;
+    for (int mu = 0; mu < 4; ++mu) {
+      double2* d = dst + (size_t)mu * (ts + 1) * u_plane();
+      const double2* src = U + (size_t)mu * T * u_plane();
+      int done = 0;
+      const int first = t0_of(k) - 1;
+      while (done < n) {
+        const int tp = ((first + done) % T + T) % T;
+        const int run = std::min(n - done, T - tp);
+        OOC_TRY(hipMemcpyAsync(d + (size_t)done * u_plane(), src + (size_t)tp * u_plane(),
+                               (size_t)run * u_plane() * sizeof(double2), hipMemcpyHostToDevice, s));
+        done += run;
+      }
+    }
+    return WD_OK;
+  }
+  SlabGeom geom_of(int k) const {
+    SlabGeom g = sg;
+    g.ts = ts_of(k);
+    return g;
+  }
+  CanonGauge gauge_of(const OocSet& S) const {
+    CanonGauge G;
+    G.data = S.U;
+    G.V = (size_t)(ts + 1) * plane;
+    return G;
+  }
+  CanonSpinor win_of(const OocSet& S) const {
+    CanonSpinor c;
+    c.data = S.win;
+    return c;
+  }
+  // every slab launches the full slab's workgroups (a thinner last slab's
+  // extra ones store zero partials), so that no stale partial is summed
+  unsigned grid_of(int) const { return (unsigned)blocks_per_slab(ts, plane); }
+
+  // One pass over the slabs. `in` queues slab k's copies into buffer set S on
+  // the copy-in stream, `kern` its kernel on the kernel stream, `out` its
+  // write-back on the copy-out stream. `window`: slab k reads host data of
+  // slabs k - 1 and k + 1 too.
+  template <class In, class Kern, class Out>
+  int sweep(bool window, In in, Kern kern, Out out) {
+    if (window) start = (start + 1) % nslab;
+    OocDevice& D = *dev;
+    for (int i = 0; i < nslab; ++i) {
+      const int k = (start + i) % nslab;
+      const int j = i & 1;
+      OocSet& S = L.set[j];
+      OOC_TRY(hipStreamWaitEvent(D.h2d, set_free[j], 0));
+      OOC_TRY(hipStreamWaitEvent(D.h2d, out_ev[k], 0));
+      if (window) {
+        OOC_TRY(hipStreamWaitEvent(D.h2d, out_ev[(k + nslab - 1) % nslab], 0));
+        OOC_TRY(hipStreamWaitEvent(D.h2d, out_ev[(k + 1) % nslab], 0));
+      }
+      int rc = in(k, S, D.h2d);
+      if (rc) return rc;
+      OOC_TRY(hipEventRecord(in_ready[j], D.h2d));
+      OOC_TRY(hipStreamWaitEvent(D.comp, in_ready[j], 0));
+      kern(k, S, D.comp);
+      OOC_TRY(hipGetLastError());
+      OOC_TRY(hipEventRecord(comp_done[j], D.comp));
+      OOC_TRY(hipStreamWaitEvent(D.d2h, comp_done[j], 0));
+      if ((rc = out(k, S, D.d2h))) return rc;
+      OOC_TRY(hipEventRecord(out_ev[k], D.d2h));
+      OOC_TRY(hipEventRecord(set_free[j], D.d2h));
+    }
+    return WD_OK;
+  }
+  void finalize(int fin) { launch_finalize_n(total_partials(), L.partials, L.st, fin, G_ALWAYS, dev->comp); }
+
+  // ---- the sweeps of the solver
+  // b' = D^+ b (source) or b (normal); r = p = b'; ||b'||^2 -> bnorm, rho; x = 0 if asked
+  int sweep_setup(bool source, bool zero_x) {
+    auto in = [&](int k, OocSet& S, hipStream_t s) {
+      return source ? (links_in(S.U, k, s) || window_in(S.win, b, k, s) ? WD_ERR_HIP : WD_OK) : slab_in(S.s[0], b, k, s);
+    };
+    auto kern = [&](int k, OocSet& S, hipStream_t s) {
+      if (source)
+        k_ooc_apply<true><<<grid_of(k), kBlock, 0, s>>>(geom_of(k), gauge_of(S), win_of(S), S.s[0], diag,
+                                                        partials_of(k));
+      else
+        k_ooc_norm2<<<grid_of(k), kBlock, 0, s>>>(ts_of(k) * plane, S.s[0], partials_of(k));
+      if (zero_x) (void)hipMemsetAsync(S.s[1], 0, (size_t)ts_of(k) * sp_plane() * sizeof(double2), s);
+    };
+    auto out = [&](int k, OocSet& S, hipStream_t s) {
+      if (slab_out(bp, S.s[0], k, s) || slab_out(r, S.s[0], k, s) || slab_out(p, S.s[0], k, s)) return WD_ERR_HIP;
+      if (zero_x && slab_out(x, S.s[1], k, s)) return WD_ERR_HIP;
+      return WD_OK;
+    };
+    int rc = sweep(source, in, kern, out);
+    if (rc) return rc;
+    finalize(F_BNORM);
+    finalize(F_RHO_INIT);
+    return WD_OK;
+  }
+  // t = D v (v = p in the iteration, x for a residual); ||t||^2 -> fin
+  int sweep_D(const double2* v, int fin) {
+    auto in = [&](int k, OocSet& S, hipStream_t s) {
+      return (links_in(S.U, k, s) || window_in(S.win, v, k, s)) ? WD_ERR_HIP : WD_OK;
+    };
+    auto kern = [&](int k, OocSet& S, hipStream_t s) {
+      k_ooc_apply<false><<<grid_of(k), kBlock, 0, s>>>(geom_of(k), gauge_of(S), win_of(S), S.s[0], diag,
+                                                       partials_of(k));
+    };
+    auto out = [&](int k, OocSet& S, hipStream_t s) { return slab_out(t, S.s[0], k, s); };
+    int rc = sweep(true, in, kern, out);
+    if (rc) return rc;
+    if (fin != F_NONE) finalize(fin);
+    return WD_OK;
+  }
+  // q = D^+ t; x += alpha p; r -= alpha q; ||r||^2 -> beta
+  int sweep_update() {
+    auto in = [&](int k, OocSet& S, hipStream_t s) {
+      return (links_in(S.U, k, s) || window_in(S.win, t, k, s) || slab_in(S.s[0], x, k, s) ||
+              slab_in(S.s[1], p, k, s) || slab_in(S.s[2], r, k, s))
+                 ? WD_ERR_HIP
+                 : WD_OK;
+    };
+    auto kern = [&](int k, OocSet& S, hipStream_t s) {
+      k_ooc_update<<<grid_of(k), kBlock, 0, s>>>(geom_of(k), gauge_of(S), win_of(S), S.s[0], S.s[1], S.s[2], diag,
+                                                 L.st, partials_of(k));
+    };
+    auto out = [&](int k, OocSet& S, hipStream_t s) {
+      return (slab_out(x, S.s[0], k, s) || slab_out(r, S.s[2], k, s)) ? WD_ERR_HIP : WD_OK;
+    };
+    int rc = sweep(true, in, kern, out);
+    if (rc) return rc;
+    finalize(F_BETA);
+    return WD_OK;
+  }
+  // p = r + beta p
+  int sweep_p_update() {
+    auto in = [&](int k, OocSet& S, hipStream_t s) {
+      return (slab_in(S.s[0], r, k, s) || slab_in(S.s[1], p, k, s)) ? WD_ERR_HIP : WD_OK;
+    };
+    auto kern = [&](int k, OocSet& S, hipStream_t s) {
+      const size_t n = (size_t)ts_of(k) * sp_plane();
+      k_ooc_p_update<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(n, S.s[0], S.s[1], L.st);
+    };
+    auto out = [&](int k, OocSet& S, hipStream_t s) { return slab_out(p, S.s[1], k, s); };
+    return sweep(false, in, kern, out);
+  }
+  // r = b' - D^+ t (p = r too when restart); ||r||^2 -> fin
+  int sweep_residual(int fin, bool set_p) {
+    auto in = [&](int k, OocSet& S, hipStream_t s) {
+      return (links_in(S.U, k, s) || window_in(S.win, t, k, s) || slab_in(S.s[0], bp, k, s)) ? WD_ERR_HIP : WD_OK;
+    };
+    auto kern = [&](int k, OocSet& S, hipStream_t s) {
+      k_ooc_residual<<<grid_of(k), kBlock, 0, s>>>(geom_of(k), gauge_of(S), win_of(S), S.s[0], S.s[1],
+                                                   set_p ? S.s[2] : nullptr, diag, partials_of(k));
+    };
+    auto out = [&](int k, OocSet& S, hipStream_t s) {
+      if (slab_out(r, S.s[1], k, s)) return WD_ERR_HIP;
+      if (set_p && slab_out(p, S.s[2], k, s)) return WD_ERR_HIP;
+      return WD_OK;
+    };
+    int rc = sweep(true, in, kern, out);
+    if (rc) return rc;
+    finalize(fin);
+    return WD_OK;
+  }
+  // the device state, after everything queued so far on the kernel stream
+  int post_state() {
+    OOC_TRY(hipMemcpyAsync(dev->mirror, L.st, sizeof(SolverState), hipMemcpyDeviceToHost, dev->comp));
+    OOC_TRY(hipEventRecord(dev->mirror_ev, dev->comp));
+    return WD_OK;
+  }
+  int wait_state(SolverState* out) {
+    OOC_TRY(hipEventSynchronize(dev->mirror_ev));
+    *out = *dev->mirror;
+    return WD_OK;
+  }
+};
+
+}  // namespace
+
+size_t ooc_device_bytes(const int L[4], int slab_planes, int hist_len) {
+  const int plane = L[0] * L[1] * L[2];
+  return ooc_layout(nullptr, plane, L[3], slab_planes, hist_len).bytes;
+}
+
+size_t ooc_host_bytes(const int L[4]) {
+  return 4 * (size_t)L[0] * L[1] * L[2] * L[3] * kSpinorSite;
+}
+
+int ooc_slab_planes(const int L[4], size_t device_bytes, int hist_len) {
+  const int T = L[3];
+  const int cap = std::max(1, (T + 3) / 4);   // at least about four slabs, so that copies overlap
+  int best = 0;
+  for (int ts = 1; ts <= cap; ++ts)
+    if (ooc_device_bytes(L, ts, hist_len) <= device_bytes) best = ts;
+  return best;
+}
+
+int ooc_solve(const int Ldims[4], double mass, const void* U, const void* b, void* x, const ::wd_cg_params* p,
+              ::wd_cg_result* res, void* host_ws, void* dev_ws, size_t dev_ws_bytes, hipStream_t caller,
+              char* err, size_t errlen) {
+  const auto t0 = std::chrono::steady_clock::now();
+  Ooc o;
+  o.err = err;
+  o.errlen = errlen;
+  o.T = Ldims[3];
+  o.plane = Ldims[0] * Ldims[1] * Ldims[2];
+  o.ts = ooc_slab_planes(Ldims, dev_ws_bytes, p->history_len);
+  if (o.ts < 1) {
+    snprintf(err, errlen, "device workspace of %zu bytes is below the minimum of %zu (one-plane slabs)", dev_ws_bytes,
+             ooc_device_bytes(Ldims, 1, p->history_len));
+    return WD_ERR_WORKSPACE;
+  }
+  o.nslab = (o.T + o.ts - 1) / o.ts;
+  for (int i = 0; i < 3; ++i) o.sg.L[i] = Ldims[i];
+  o.sg.plane = o.plane;
+  o.sg.dx = make_fastdiv(Ldims[0]);
+  o.sg.dy = make_fastdiv(Ldims[1]);
+  o.sg.dz = make_fastdiv(Ldims[2]);
+  o.diag = mass + 4.0;
+  o.U = static_cast<const double2*>(U);
+  o.b = static_cast<const double2*>(b);
+  o.x = static_cast<double2*>(x);
+  const size_t V = (size_t)o.plane * o.T;
+  double2* hw = static_cast<double2*>(host_ws);
+  o.bp = hw;
+  o.r = hw + V * 12;
+  o.p = hw + 2 * V * 12;
+  o.t = hw + 3 * V * 12;
+  o.L = ooc_layout(dev_ws, o.plane, o.T, o.ts, p->history_len);
+  int rc = ooc_device(&o.dev, err, errlen);
+  if (rc) return rc;
+  OocDevice& D = *o.dev;
+
+  // events of this solve (recorded once so that the first waits pass)
+  std::vector<hipEvent_t> evs;
+  auto make_ev = [&](hipEvent_t* e) -> int {
+    OOC_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
+    evs.push_back(*e);
+    return WD_OK;
+  };
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(D.h2d);
+    (void)hipStreamSynchronize(D.comp);
+    (void)hipStreamSynchronize(D.d2h);
+    for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+  };
+  o.out_ev.assign(o.nslab, nullptr);
+  for (int k = 0; k < o.nslab && !rc; ++k) rc = make_ev(&o.out_ev[k]);
+  for (int j = 0; j < 2 && !rc; ++j)
+    rc = make_ev(&o.in_ready[j]) || make_ev(&o.comp_done[j]) || make_ev(&o.set_free[j]) ? WD_ERR_HIP : WD_OK;
+  hipEvent_t caller_ev = nullptr;
+  if (!rc) rc = make_ev(&caller_ev);
+  if (rc) {
+    cleanup();
+    return rc;
+  }
+  // everything after the caller's queued work
+  auto run = [&]() -> int {
+    OOC_TRY(hipEventRecord(caller_ev, caller));
+    OOC_TRY(hipStreamWaitEvent(D.h2d, caller_ev, 0));
+    OOC_TRY(hipStreamWaitEvent(D.comp, caller_ev, 0));
+    OOC_TRY(hipStreamWaitEvent(D.d2h, caller_ev, 0));
+    for (hipEvent_t e : o.out_ev) OOC_TRY(hipEventRecord(e, D.d2h));
+    for (int j = 0; j < 2; ++j) OOC_TRY(hipEventRecord(o.set_free[j], D.d2h));
+
+    launch_init_state(o.L.st, p->tol, 0, 0.0, o.L.hist, p->history_len, D.comp);
+    const bool source = p->rhs_mode == WD_RHS_SOURCE;
+    int r2 = o.sweep_setup(source, p->zero_guess != 0);
+    if (r2) return r2;
+    if (!p->zero_guess) {
+      // r = b' - D^+ D x0, p = r
+      if ((r2 = o.sweep_D(o.x, F_NONE)) || (r2 = o.sweep_residual(F_RHO_INIT, true))) return r2;
+    }
+    SolverState st{};
+    if ((r2 = o.post_state()) || (r2 = o.wait_state(&st))) return r2;
+    int restarts = 0;
+    while (st.status == 0 && st.iter < p->max_iter) {
+      if ((r2 = o.sweep_D(o.p, F_ALPHA)) || (r2 = o.sweep_update())) return r2;
+      if ((r2 = o.post_state())) return r2;
+      if ((r2 = o.sweep_p_update())) return r2;   // queued before the host looks
+      if ((r2 = o.wait_state(&st))) return r2;
+      if (st.status == 1) {
+        // confirm with the residual recomputed from x
+        if ((r2 = o.sweep_D(o.x, F_NONE)) || (r2 = o.sweep_residual(F_TRUE, true))) return r2;
+        if ((r2 = o.post_state()) || (r2 = o.wait_state(&st))) return r2;
+        if (st.rho_true <= st.stop2 || st.iter >= p->max_iter || restarts >= 5) break;
+        ++restarts;   // the recurrence drifted: continue from the recomputed residual (r = p = it)
+        launch_restart(o.L.st, D.comp);
+        if ((r2 = o.post_state()) || (r2 = o.wait_state(&st))) return r2;
+      }
+    }
+    if (st.status == 0 || (st.status == 1 && st.rho_true > st.stop2)) {
+      // stopped by max_iter: the true residual of the last iterate
+      if ((r2 = o.sweep_D(o.x, F_NONE)) || (r2 = o.sweep_residual(F_TRUE, false))) return r2;
+      if ((r2 = o.post_state()) || (r2 = o.wait_state(&st))) return r2;
+    }
+    if (p->history && p->history_len > 0) {
+      const int n = std::min(st.iter, p->history_len);
+      if (n > 0) {
+        OOC_TRY(hipMemcpyAsync(p->history, o.L.hist, sizeof(double) * n, hipMemcpyDeviceToHost, D.comp));
+        OOC_TRY(hipStreamSynchronize(D.comp));
+      }
+      for (int i = n; i < p->history_len; ++i) p->history[i] = 0.0;
+    }
+    OOC_TRY(hipStreamSynchronize(D.h2d));
+    OOC_TRY(hipStreamSynchronize(D.comp));
+    OOC_TRY(hipStreamSynchronize(D.d2h));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    const double bn = st.bnorm2 > 0 ? st.bnorm2 : 1.0;
+    int code;
+    if (st.status == -3) code = WD_ERR_BREAKDOWN;
+    else if (st.status == -4) code = WD_ERR_NAN;
+    else if (st.rho_true <= st.stop2 && st.status == 1) code = WD_OK;
+    else code = WD_NOT_CONVERGED;
+    if (code == WD_ERR_BREAKDOWN) snprintf(err, errlen, "CG breakdown: <p, A p> <= 0");
+    if (code == WD_ERR_NAN) snprintf(err, errlen, "NaN or Inf encountered in a CG reduction");
+    if (code == WD_NOT_CONVERGED)
+      snprintf(err, errlen, "not converged in %d iterations (true rel. residual %.3e)", st.iter,
+               std::sqrt(st.rho_true / bn));
+    if (res) {
+      res->iterations = st.iter;
+      res->reliable_updates = 0;
+      res->status = code;
+      res->two_row_links = 0;
+      res->true_rel_res = std::sqrt(st.rho_true / bn);
+      res->iter_rel_res = std::sqrt(st.rho / bn);
+      res->seconds = secs;
+      for (int j = 0; j < 3; ++j) res->kernel_seconds[j] = 0.0;
+      res->ooc_slab_planes = o.ts;
+      res->ooc_slabs = o.nslab;
+    }
+    return code;
+  };
+  rc = run();
+  cleanup();
+  return rc;
+}
+
+}  // namespace wd

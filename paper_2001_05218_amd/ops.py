@@ -324,3 +324,71 @@ def wilson_apply_packed(U_packed: torch.Tensor, in_packed: torch.Tensor, out_pac
                                  U_packed.data_ptr(), in_packed.data_ptr(), out_packed.data_ptr(),
                                  1 if dagger else 0, s)
     _lib.check(rc, "wilson_apply_packed")
+
+
+# ---- out-of-core solve: host-resident fields streamed through the GPU in t-slabs
+
+def _need_pinned(t: torch.Tensor, name: str, shape=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a tensor")
+    if t.device.type != "cpu" or not t.is_pinned():
+        raise ValueError(f"{name} must be a pinned host tensor (torch.empty(..., pin_memory=True) or .pin_memory())")
+    if t.dtype != torch.complex128:
+        raise TypeError(f"{name} has dtype {t.dtype}, expected torch.complex128")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def ooc_workspace_bytes(dims, slab_planes: int, history_len: int = 0):
+    """(device bytes, pinned host bytes) of an out-of-core solve whose slabs hold
+    `slab_planes` time planes."""
+    lib = _lib.load()
+    dev = ctypes.c_size_t(0)
+    host = ctypes.c_size_t(0)
+    rc = lib.wd_ooc_workspace_bytes(ctypes.byref(_lib.lattice(dims)), int(slab_planes), int(history_len),
+                                    ctypes.byref(dev), ctypes.byref(host))
+    _lib.check(rc, "wd_ooc_workspace_bytes")
+    return int(dev.value), int(host.value)
+
+
+def cg_solve_ooc(U: torch.Tensor, b: torch.Tensor, mass: float, tol: float = 1e-10, max_iter: int = 10000,
+                 rhs: str = "source", x0: torch.Tensor | None = None, history: int = 0,
+                 device_bytes: int | None = None, device_workspace: torch.Tensor | None = None,
+                 host_workspace: torch.Tensor | None = None, device=None, raise_on_nonconvergence: bool = True):
+    """FP64 CG on D^+D x = D^+b (or b) with U, b and x in pinned HOST memory, streamed
+    through the GPU in t-slabs. The device holds at most `device_bytes` (or the
+    given device_workspace); the CG vectors live in a pinned host workspace.
+    Returns (x, info) with x a pinned host tensor."""
+    dims = dims_of_spinor(b)
+    _need_pinned(b, "b", spinor_shape(dims))
+    _need_pinned(U, "U", gauge_shape(dims))
+    dev = torch.device(device if device is not None else "cuda")
+    params, hist = make_params(tol, max_iter, "f64", 50, rhs, WD_C128, x0 is None, history)
+    if x0 is None:
+        x = torch.empty(b.shape, dtype=torch.complex128, pin_memory=True)
+    else:
+        _need_pinned(x0, "x0", b.shape)
+        x = torch.empty(b.shape, dtype=torch.complex128, pin_memory=True)
+        x.copy_(x0)
+    _, host_need = ooc_workspace_bytes(dims, 1, history)
+    if host_workspace is None or host_workspace.numel() < host_need:
+        host_workspace = torch.empty(host_need, dtype=torch.uint8, pin_memory=True)
+    if device_workspace is None:
+        if device_bytes is None:
+            raise ValueError("give device_bytes (the device memory budget) or a device_workspace")
+        device_workspace = torch.empty(int(device_bytes), dtype=torch.uint8, device=dev)
+    res = _lib.WdCgResult()
+    lib = _lib.load()
+    with torch.cuda.device(device_workspace.device):
+        rc = lib.cg_solve_ooc(ctypes.byref(_lib.lattice(dims)), float(mass), U.data_ptr(), b.data_ptr(),
+                              x.data_ptr(), ctypes.byref(params), ctypes.byref(res), host_workspace.data_ptr(),
+                              host_workspace.numel(), device_workspace.data_ptr(), device_workspace.numel(),
+                              _stream(device_workspace.device))
+    ok = (_lib.WD_OK,) if raise_on_nonconvergence else (_lib.WD_OK, _lib.WD_NOT_CONVERGED)
+    _lib.check(rc, "cg_solve_ooc", ok)
+    info = res.as_dict()
+    if hist is not None:
+        info["history"] = list(hist)[: min(history, res.iterations)]
+    return x, info

@@ -1,0 +1,149 @@
+"""Out-of-core CG (cg_solve_ooc): U, b and x in pinned host memory, streamed
+through the GPU in t-slabs under a device-memory budget; checked against the
+oracle and against the in-HBM solver.
+
+Budgets are chosen so that slabs are one or a few time planes thick, with a
+ragged last slab, a lattice of extent 2 in t (the two halo planes of a slab are
+then the same plane), odd extents, and the c1 lattice under 64 MiB.
+"""
+import numpy as np
+import pytest
+import torch
+
+import fieldgen
+import oracle
+from gpu_util import log, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+wd = pytest.importorskip("paper_2001_05218_amd")
+_lib = wd._lib
+
+TOL = 1e-10
+
+
+def _pinned(a: np.ndarray) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
+
+
+def _budget(dims, slab_planes, history=0):
+    dev, _ = wd.ooc_workspace_bytes(dims, slab_planes, history)
+    return dev
+
+
+def test_workspace_sizes_grow_with_slab_thickness():
+    dims = (8, 8, 8, 16)
+    d1, h1 = wd.ooc_workspace_bytes(dims, 1)
+    d2, h2 = wd.ooc_workspace_bytes(dims, 2)
+    assert d2 > d1 and h1 == h2 == 4 * 8 * 8 * 8 * 16 * 192
+
+
+def test_config0_matches_oracle_cg_history():
+    # 4^4 Haar, m = 0.1: one-plane slabs (four of them); FP64 CGNR is the
+    # oracle's recurrence, so the iteration count and residual history agree
+    dims, mass = (4, 4, 4, 4), 0.1
+    U = fieldgen.gauge_field(dims, "haar", 200105218)
+    b = fieldgen.gaussian_spinor(dims, 200105219)
+    x, info = wd.cg_solve_ooc(_pinned(U), _pinned(b), mass, tol=TOL, history=200,
+                              device_bytes=_budget(dims, 1, 200))
+    assert info["ooc_slab_planes"] == 1 and info["ooc_slabs"] == 4
+    xr, ir = oracle.cgnr(U, b, mass, tol=TOL, history=True)
+    log(f"ooc c0: {info['iterations']} it (oracle {ir['iterations']}), true res {info['true_rel_res']:.3e}")
+    assert info["iterations"] == ir["iterations"]
+    h = np.array(info["history"])
+    assert np.allclose(h, ir["history"], rtol=1e-6, atol=0)
+    xn = x.numpy()
+    assert oracle.true_relative_residual(U, xn, b, mass) <= TOL * (1 + 1e-3)
+    assert np.linalg.norm(xn - xr) <= 1e-8 * np.linalg.norm(xr)
+
+
+@pytest.mark.parametrize("dims,planes,kind", [((5, 3, 7, 7), 2, "haar"),        # slabs 2, 2, 2, 1
+                                              ((4, 4, 4, 2), 1, "near_identity"),  # t extent 2
+                                              ((6, 4, 2, 9), 3, "haar")])         # three slabs of 3
+def test_odd_lattices_against_oracle(dims, planes, kind):
+    mass = 0.07
+    U = fieldgen.gauge_field(dims, kind, 77)
+    b = fieldgen.gaussian_spinor(dims, 78)
+    x, info = wd.cg_solve_ooc(_pinned(U), _pinned(b), mass, tol=TOL, device_bytes=_budget(dims, planes))
+    assert info["ooc_slab_planes"] == planes
+    assert info["ooc_slabs"] == -(-dims[3] // planes)
+    res = oracle.true_relative_residual(U, x.numpy(), b, mass)
+    log(f"ooc {dims} slabs of {planes}: {info['iterations']} it, oracle residual {res:.3e}")
+    assert res <= TOL * (1 + 1e-3)
+    assert abs(res - info["true_rel_res"]) <= 1e-13
+
+
+def test_normal_mode_and_initial_guess():
+    dims, mass = (4, 6, 2, 8), 0.2
+    U = fieldgen.gauge_field(dims, "haar", 81)
+    b = fieldgen.gaussian_spinor(dims, 82)
+    x0 = fieldgen.gaussian_spinor(dims, 83)
+    x, info = wd.cg_solve_ooc(_pinned(U), _pinned(b), mass, tol=TOL, rhs="normal", x0=_pinned(x0),
+                              device_bytes=_budget(dims, 2))
+    res = oracle.true_relative_residual(U, x.numpy(), b, mass, rhs="normal")
+    assert res <= TOL * (1 + 1e-3)
+    xd = oracle.dense_solve_normal(U, b, mass, dims, rhs="normal") if np.prod(dims) <= 256 else None
+    if xd is not None:
+        assert np.linalg.norm(x.numpy() - xd) <= 1e-7 * np.linalg.norm(xd)
+
+
+def test_max_iter_then_resume():
+    dims, mass = (4, 4, 4, 8), 0.05
+    U = _pinned(fieldgen.gauge_field(dims, "near_identity", 91))
+    b = _pinned(fieldgen.gaussian_spinor(dims, 92))
+    budget = _budget(dims, 2)
+    x1, i1 = wd.cg_solve_ooc(U, b, mass, tol=TOL, max_iter=10, device_bytes=budget, raise_on_nonconvergence=False)
+    assert i1["status"] == _lib.WD_NOT_CONVERGED and i1["iterations"] == 10
+    # the reported residual is the true one of the returned iterate
+    assert abs(oracle.true_relative_residual(U.numpy(), x1.numpy(), b.numpy(), mass) - i1["true_rel_res"]) <= 1e-13
+    x2, i2 = wd.cg_solve_ooc(U, b, mass, tol=TOL, x0=x1, device_bytes=budget)
+    assert oracle.true_relative_residual(U.numpy(), x2.numpy(), b.numpy(), mass) <= TOL * (1 + 1e-3)
+
+
+def test_zero_and_nan_sources():
+    dims, mass = (4, 4, 4, 4), 0.1
+    U = _pinned(fieldgen.gauge_field(dims, "haar", 5))
+    budget = _budget(dims, 1)
+    z = torch.zeros(fieldgen.lattice_shape(dims) + (4, 3), dtype=torch.complex128).pin_memory()
+    x, info = wd.cg_solve_ooc(U, z, mass, device_bytes=budget)
+    assert info["iterations"] == 0 and torch.count_nonzero(x) == 0
+    bn = fieldgen.gaussian_spinor(dims, 6)
+    bn[1, 2, 3, 0, 2, 1] = np.nan
+    with pytest.raises(_lib.WilsonError) as e:
+        wd.cg_solve_ooc(U, _pinned(bn), mass, device_bytes=budget)
+    assert e.value.code == _lib.WD_ERR_NAN
+
+
+def test_arguments_refused_before_any_work():
+    dims = (4, 4, 4, 4)
+    U = _pinned(fieldgen.gauge_field(dims, "haar", 5))
+    b = _pinned(fieldgen.gaussian_spinor(dims, 6))
+    with pytest.raises(_lib.WilsonError) as e:   # below the one-plane minimum
+        wd.cg_solve_ooc(U, b, 0.1, device_bytes=_budget(dims, 1) - 4096)
+    assert e.value.code == _lib.WD_ERR_WORKSPACE
+    with pytest.raises(ValueError):              # pageable host memory, refused by the binding
+        wd.cg_solve_ooc(U, torch.from_numpy(fieldgen.gaussian_spinor(dims, 6)), 0.1, device_bytes=1 << 26)
+
+
+def test_c1_lattice_under_64_mib_matches_in_hbm_solve():
+    # 16^3 x 32, links exp(i 0.3 H), m = 0.05: 75.5 MB of links and 25 MB per
+    # vector, solved with 64 MiB of device memory; the same FP64 CGNR as
+    # cg_solve in HBM, so the solutions agree to the solve's accuracy
+    dims, mass = (16, 16, 16, 32), 0.05
+    U = fieldgen.gauge_field(dims, "near_identity", 200105228, eps=0.3)
+    b = fieldgen.gaussian_spinor(dims, 200105229)
+    x, info = wd.cg_solve_ooc(_pinned(U), _pinned(b), mass, tol=TOL, max_iter=5000, device_bytes=64 << 20)
+    log(f"ooc c1: {info['iterations']} it, {info['ooc_slabs']} slabs of {info['ooc_slab_planes']} planes, "
+        f"{info['seconds']:.3f} s, true res {info['true_rel_res']:.3e}")
+    assert info["ooc_slabs"] >= 4
+    xh, ih = wd.cg_solve(to_dev(U), to_dev(b), mass, tol=TOL, max_iter=5000)
+    log(f"  in HBM: {ih['iterations']} it, {ih['seconds']:.3f} s")
+    assert abs(info["iterations"] - ih["iterations"]) <= 2
+    xn = x.numpy()
+    res = oracle.true_relative_residual(U, xn, b, mass)
+    log(f"  oracle residual {res:.3e}")
+    assert res <= TOL * (1 + 1e-3)
+    xhn = to_np(xh)
+    d = float(np.linalg.norm(xn - xhn) / np.linalg.norm(xhn))
+    log(f"  relative difference to the in-HBM solution {d:.3e}")
+    assert d <= 1e-5

@@ -39,7 +39,7 @@ def test_struct_layouts_match_header():
     # sizes of the structs as laid out by a C compiler for the header
     assert ctypes.sizeof(_lib.WdLattice) == 16
     assert ctypes.sizeof(_lib.WdCgParams) == 72
-    assert ctypes.sizeof(_lib.WdCgResult) == 64
+    assert ctypes.sizeof(_lib.WdCgResult) == 72
 
 
 def _lat(dims):
@@ -239,3 +239,30 @@ def test_lockstep_workspace_grows_by_one_region_per_system(lib):
     step = steps.pop()
     assert step % 256 == 0 and step > 0
     assert sizes[0] > step   # the shared part comes on top of system 0's region
+
+
+def test_ooc_workspace_sizes(lib):
+    dims = (8, 8, 8, 16)
+    dev = [ctypes.c_size_t(0) for _ in range(3)]
+    host = ctypes.c_size_t(0)
+    for ts, d in zip((1, 2, 4), dev):
+        assert lib.wd_ooc_workspace_bytes(_lat(dims), ts, 0, ctypes.byref(d), ctypes.byref(host)) == 0
+    assert dev[0].value < dev[1].value < dev[2].value
+    assert host.value == 4 * 8 * 8 * 8 * 16 * 192          # b', r, p, t in FP64
+    # two buffer sets of 4 (ts + 1) link planes and 3 ts + ts + 2 spinor planes,
+    # so one more plane per slab costs at least 2 (4 x 144 + 4 x 192) B per site
+    plane = 8 * 8 * 8
+    assert dev[1].value - dev[0].value >= 2 * plane * (4 * 144 + 4 * 192)
+    for bad in (0, 17):
+        assert lib.wd_ooc_workspace_bytes(_lat(dims), bad, 0, None, None) == _lib.WD_ERR_INVALID
+
+
+def test_stream_rejects_bad_args(lib):
+    buf = ctypes.create_string_buffer(64)
+    p = ctypes.addressof(buf)
+    p16 = (p + 15) & ~15
+    assert lib.wd_stream(3, p16, p16, 16, None) == _lib.WD_ERR_INVALID        # unknown kind
+    assert lib.wd_stream(0, p16, p16, 24, None) == _lib.WD_ERR_INVALID        # not a multiple of 16
+    assert lib.wd_stream(0, p16 + 8, p16, 16, None) == _lib.WD_ERR_INVALID    # misaligned
+    assert lib.wd_stream(0, None, p16, 16, None) == _lib.WD_ERR_INVALID       # NULL
+    assert lib.wd_stream_partials(1 << 33) >= 1
