@@ -266,8 +266,10 @@ int wilson_force(const wd_lattice* lat, const void* a, const void* b, double coe
  * streams the lattice through the GPU in slabs of whole time planes (each slab
  * with one halo plane on either side, periodic in t), on three HIP streams
  * (copies in, kernels, copies out) and two device buffer sets, so that copies
- * of neighbouring slabs overlap the kernels. One iteration moves about
- * 2.5 KB per site to the device and 0.8 KB back. */
+ * of neighbouring slabs overlap the kernels. The copies are kernels that read
+ * and write the pinned host memory in place (one launch per slab and
+ * direction). One iteration moves about 2.5 KB per site to the device and
+ * 0.8 KB back. */
 
 /* Workspace of cg_solve_ooc for slabs of slab_planes time planes
  * (1 <= slab_planes <= Lt) and a residual history of history_len entries:

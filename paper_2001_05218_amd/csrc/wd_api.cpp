@@ -1284,15 +1284,19 @@ extern "C" int cg_solve_noalloc(const wd_lattice* lat, double mass, const void* 
 
 namespace {
 
-// Host memory the GPU can copy from asynchronously: pinned (page-locked) and
-// known to the HIP runtime.
-bool pinned_host(const void* p) {
+// Host memory the GPU can read and write in place: pinned (page-locked) and
+// known to the HIP runtime. *dev receives the address kernels use for it.
+bool pinned_host(const void* p, const void** dev) {
   hipPointerAttribute_t a{};
   if (hipPointerGetAttributes(&a, p) != hipSuccess) {
     (void)hipGetLastError();   // pageable memory: clear the error the query left
     return false;
   }
-  return a.type == hipMemoryTypeHost;
+  if (a.type != hipMemoryTypeHost) return false;
+  *dev = p;
+  if (a.devicePointer && a.hostPointer)
+    *dev = static_cast<const char*>(a.devicePointer) + (static_cast<const char*>(p) - static_cast<const char*>(a.hostPointer));
+  return true;
 }
 
 }  // namespace
@@ -1323,9 +1327,10 @@ extern "C" int cg_solve_ooc(const wd_lattice* lat, double mass, const void* U, c
   if (b == x) return fail(WD_ERR_INVALID, "b and x must not alias");
   if (!std::isfinite(mass)) return fail(WD_ERR_INVALID, "mass is not finite");
   const void* host_ptrs[4] = {U, b, x, host_workspace};
+  const void* dev_ptrs[4] = {nullptr, nullptr, nullptr, nullptr};
   const char* names[4] = {"U", "b", "x", "host_workspace"};
   for (int i = 0; i < 4; ++i)
-    if (!pinned_host(host_ptrs[i]))
+    if (!pinned_host(host_ptrs[i], &dev_ptrs[i]))
       return fail(WD_ERR_INVALID, "cg_solve_ooc: %s is not pinned host memory (hipHostMalloc or a pinned tensor)",
                   names[i]);
   const size_t host_need = ooc_host_bytes(lat->L);
@@ -1337,7 +1342,9 @@ extern "C" int cg_solve_ooc(const wd_lattice* lat, double mass, const void* U, c
   std::unique_lock<std::mutex> lk;
   if ((rc = lock_device(lk))) return rc;
   char err[512] = {0};
-  rc = ooc_solve(lat->L, mass, U, b, x, params, result, host_workspace, device_workspace, device_ws_bytes,
+  // the kernels read and write the host fields in place, through their device addresses
+  rc = ooc_solve(lat->L, mass, dev_ptrs[0], dev_ptrs[1], const_cast<void*>(dev_ptrs[2]),
+                 params, result, const_cast<void*>(dev_ptrs[3]), device_workspace, device_ws_bytes,
                  as_stream(stream), err, sizeof(err));
   if (rc != WD_OK) return fail(rc, "%s", err);
   return WD_OK;

@@ -177,6 +177,42 @@ __global__ __launch_bounds__(kBlock) void k_ooc_norm2(int n, const double2* __re
   store_partial(n2, partials);
 }
 
+// Copies between pinned host memory and device memory as one kernel: up to
+// kMaxSeg segments of 16-byte words, each word one lane's coalesced load and
+// store (consecutive lanes, consecutive addresses), eight words in flight per
+// thread. Host memory is read and written in place over the host link; one
+// launch per slab replaces the slab's separate runtime copies, each of which
+// cost tens of microseconds of set-up between transfers.
+constexpr int kMaxSeg = 16;   // a slab's largest list: 8 link pieces, 3 window pieces, 3 slabs
+struct SegList {
+  const uint4* src[kMaxSeg];
+  uint4* dst[kMaxSeg];
+  size_t start[kMaxSeg + 1];   // prefix sums of the segments' words
+  int n;
+};
+
+__global__ __launch_bounds__(kBlock) void k_ooc_move(SegList L) {
+  const size_t total = L.start[L.n];
+  const size_t stride = (size_t)gridDim.x * kBlock * 8;
+  for (size_t base = (size_t)blockIdx.x * kBlock * 8 + threadIdx.x; base < total; base += stride) {
+    uint4 v[8];
+    int seg[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const size_t w = base + (size_t)u * kBlock;
+      int k = 0;
+      while (k + 1 < L.n && w >= L.start[k + 1]) ++k;
+      seg[u] = k;
+      if (w < total) v[u] = L.src[k][w - L.start[k]];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const size_t w = base + (size_t)u * kBlock;
+      if (w < total) L.dst[seg[u]][w - L.start[seg[u]]] = v[u];
+    }
+  }
+}
+
 // ------------------------------------------------------------------ layout
 
 namespace {
@@ -292,35 +328,59 @@ struct Ooc {
   double* partials_of(int k) const { return L.partials + (size_t)k * blocks_per_slab(ts, plane); }
   int total_partials() const { return nslab * blocks_per_slab(ts, plane); }
 
+  // A pending list of copies for one k_ooc_move launch.
+  struct Moves {
+    SegList L{};
+    size_t words = 0;
+  };
+  bool overflow = false;
+  void add(Moves& m, void* dst, const void* src, size_t bytes) {
+    if (!bytes) return;
+    SegList& L = m.L;
+    if (L.n == kMaxSeg) {   // cannot happen with the sweeps below (at most 14 pieces)
+      overflow = true;
+      return;
+    }
+    L.src[L.n] = static_cast<const uint4*>(src);
+    L.dst[L.n] = static_cast<uint4*>(dst);
+    L.start[L.n] = m.words;
+    m.words += bytes / 16;
+    L.n += 1;
+    L.start[L.n] = m.words;
+  }
+  int launch_moves(Moves& m, hipStream_t s) {
+    if (overflow) {
+      snprintf(err, errlen, "internal: more than %d copy segments for one slab", kMaxSeg);
+      return WD_ERR_HIP;
+    }
+    if (m.L.n == 0) return WD_OK;
+    const size_t per = (size_t)kBlock * 8;
+    const size_t blocks = std::min<size_t>((m.words + per - 1) / per, 1024);
+    k_ooc_move<<<(unsigned)blocks, kBlock, 0, s>>>(m.L);
+    OOC_TRY(hipGetLastError());
+    return WD_OK;
+  }
   // planes [first, first + n) of a host spinor field (first may be -1 or T:
   // periodic) into consecutive device planes
-  int copy_planes_in(double2* dst, const double2* src, int first, int n, hipStream_t s) {
+  void planes_in(Moves& m, double2* dst, const double2* src, int first, int n) {
     int done = 0;
     while (done < n) {
       const int tp = ((first + done) % T + T) % T;
       const int run = std::min(n - done, T - tp);
-      OOC_TRY(hipMemcpyAsync(dst + (size_t)done * sp_plane(), src + (size_t)tp * sp_plane(),
-                             (size_t)run * sp_plane() * sizeof(double2), hipMemcpyHostToDevice, s));
+      add(m, dst + (size_t)done * sp_plane(), src + (size_t)tp * sp_plane(), (size_t)run * sp_plane() * sizeof(double2));
       done += run;
     }
-    return WD_OK;
   }
-  int window_in(double2* dst, const double2* src, int k, hipStream_t s) {
-    return copy_planes_in(dst, src, t0_of(k) - 1, ts_of(k) + 2, s);
+  void window_in(Moves& m, double2* dst, const double2* src, int k) { planes_in(m, dst, src, t0_of(k) - 1, ts_of(k) + 2); }
+  void slab_in(Moves& m, double2* dst, const double2* src, int k) {
+    add(m, dst, src + (size_t)t0_of(k) * sp_plane(), (size_t)ts_of(k) * sp_plane() * sizeof(double2));
   }
-  int slab_in(double2* dst, const double2* src, int k, hipStream_t s) {
-    OOC_TRY(hipMemcpyAsync(dst, src + (size_t)t0_of(k) * sp_plane(), (size_t)ts_of(k) * sp_plane() * sizeof(double2),
-                           hipMemcpyHostToDevice, s));
-    return WD_OK;
-  }
-  int slab_out(double2* dst, const double2* src, int k, hipStream_t s) {
-    OOC_TRY(hipMemcpyAsync(dst + (size_t)t0_of(k) * sp_plane(), src, (size_t)ts_of(k) * sp_plane() * sizeof(double2),
-                           hipMemcpyDeviceToHost, s));
-    return WD_OK;
+  void slab_out(Moves& m, double2* dst, const double2* src, int k) {
+    add(m, dst + (size_t)t0_of(k) * sp_plane(), src, (size_t)ts_of(k) * sp_plane() * sizeof(double2));
   }
   // links of window planes 0 .. ts (lattice planes t0 - 1 .. t0 + ts - 1) for each mu;
   // in the device window the directions are ts_max + 1 planes apart
-  int links_in(double2* dst, int k, hipStream_t s) {
+  void links_in(Moves& m, double2* dst, int k) {
     const int n = ts_of(k) + 1;
     for (int mu = 0; mu < 4; ++mu) {
       double2* d = dst + (size_t)mu * (ts + 1) * u_plane();
@@ -330,12 +390,10 @@ struct Ooc {
       while (done < n) {
         const int tp = ((first + done) % T + T) % T;
         const int run = std::min(n - done, T - tp);
-        OOC_TRY(hipMemcpyAsync(d + (size_t)done * u_plane(), src + (size_t)tp * u_plane(),
-                               (size_t)run * u_plane() * sizeof(double2), hipMemcpyHostToDevice, s));
+        add(m, d + (size_t)done * u_plane(), src + (size_t)tp * u_plane(), (size_t)run * u_plane() * sizeof(double2));
         done += run;
       }
     }
-    return WD_OK;
   }
   SlabGeom geom_of(int k) const {
     SlabGeom g = sg;
@@ -375,7 +433,9 @@ struct Ooc {
         OOC_TRY(hipStreamWaitEvent(D.h2d, out_ev[(k + nslab - 1) % nslab], 0));
         OOC_TRY(hipStreamWaitEvent(D.h2d, out_ev[(k + 1) % nslab], 0));
       }
-      int rc = in(k, S, D.h2d);
+      Moves mi;
+      in(k, S, mi);
+      int rc = launch_moves(mi, D.h2d);
       if (rc) return rc;
       OOC_TRY(hipEventRecord(in_ready[j], D.h2d));
       OOC_TRY(hipStreamWaitEvent(D.comp, in_ready[j], 0));
@@ -383,7 +443,9 @@ struct Ooc {
       OOC_TRY(hipGetLastError());
       OOC_TRY(hipEventRecord(comp_done[j], D.comp));
       OOC_TRY(hipStreamWaitEvent(D.d2h, comp_done[j], 0));
-      if ((rc = out(k, S, D.d2h))) return rc;
+      Moves mo;
+      out(k, S, mo);
+      if ((rc = launch_moves(mo, D.d2h))) return rc;
       OOC_TRY(hipEventRecord(out_ev[k], D.d2h));
       OOC_TRY(hipEventRecord(set_free[j], D.d2h));
     }
@@ -394,8 +456,13 @@ struct Ooc {
   // ---- the sweeps of the solver
   // b' = D^+ b (source) or b (normal); r = p = b'; ||b'||^2 -> bnorm, rho; x = 0 if asked
   int sweep_setup(bool source, bool zero_x) {
-    auto in = [&](int k, OocSet& S, hipStream_t s) {
-      return source ? (links_in(S.U, k, s) || window_in(S.win, b, k, s) ? WD_ERR_HIP : WD_OK) : slab_in(S.s[0], b, k, s);
+    auto in = [&](int k, OocSet& S, Moves& m) {
+      if (source) {
+        links_in(m, S.U, k);
+        window_in(m, S.win, b, k);
+      } else {
+        slab_in(m, S.s[0], b, k);
+      }
     };
     auto kern = [&](int k, OocSet& S, hipStream_t s) {
       if (source)
@@ -405,10 +472,11 @@ struct Ooc {
         k_ooc_norm2<<<grid_of(k), kBlock, 0, s>>>(ts_of(k) * plane, S.s[0], partials_of(k));
       if (zero_x) (void)hipMemsetAsync(S.s[1], 0, (size_t)ts_of(k) * sp_plane() * sizeof(double2), s);
     };
-    auto out = [&](int k, OocSet& S, hipStream_t s) {
-      if (slab_out(bp, S.s[0], k, s) || slab_out(r, S.s[0], k, s) || slab_out(p, S.s[0], k, s)) return WD_ERR_HIP;
-      if (zero_x && slab_out(x, S.s[1], k, s)) return WD_ERR_HIP;
-      return WD_OK;
+    auto out = [&](int k, OocSet& S, Moves& m) {
+      slab_out(m, bp, S.s[0], k);
+      slab_out(m, r, S.s[0], k);
+      slab_out(m, p, S.s[0], k);
+      if (zero_x) slab_out(m, x, S.s[1], k);
     };
     int rc = sweep(source, in, kern, out);
     if (rc) return rc;
@@ -418,14 +486,15 @@ struct Ooc {
   }
   // t = D v (v = p in the iteration, x for a residual); ||t||^2 -> fin
   int sweep_D(const double2* v, int fin) {
-    auto in = [&](int k, OocSet& S, hipStream_t s) {
-      return (links_in(S.U, k, s) || window_in(S.win, v, k, s)) ? WD_ERR_HIP : WD_OK;
+    auto in = [&](int k, OocSet& S, Moves& m) {
+      links_in(m, S.U, k);
+      window_in(m, S.win, v, k);
     };
     auto kern = [&](int k, OocSet& S, hipStream_t s) {
       k_ooc_apply<false><<<grid_of(k), kBlock, 0, s>>>(geom_of(k), gauge_of(S), win_of(S), S.s[0], diag,
                                                        partials_of(k));
     };
-    auto out = [&](int k, OocSet& S, hipStream_t s) { return slab_out(t, S.s[0], k, s); };
+    auto out = [&](int k, OocSet& S, Moves& m) { slab_out(m, t, S.s[0], k); };
     int rc = sweep(true, in, kern, out);
     if (rc) return rc;
     if (fin != F_NONE) finalize(fin);
@@ -433,18 +502,20 @@ struct Ooc {
   }
   // q = D^+ t; x += alpha p; r -= alpha q; ||r||^2 -> beta
   int sweep_update() {
-    auto in = [&](int k, OocSet& S, hipStream_t s) {
-      return (links_in(S.U, k, s) || window_in(S.win, t, k, s) || slab_in(S.s[0], x, k, s) ||
-              slab_in(S.s[1], p, k, s) || slab_in(S.s[2], r, k, s))
-                 ? WD_ERR_HIP
-                 : WD_OK;
+    auto in = [&](int k, OocSet& S, Moves& m) {
+      links_in(m, S.U, k);
+      window_in(m, S.win, t, k);
+      slab_in(m, S.s[0], x, k);
+      slab_in(m, S.s[1], p, k);
+      slab_in(m, S.s[2], r, k);
     };
     auto kern = [&](int k, OocSet& S, hipStream_t s) {
       k_ooc_update<<<grid_of(k), kBlock, 0, s>>>(geom_of(k), gauge_of(S), win_of(S), S.s[0], S.s[1], S.s[2], diag,
                                                  L.st, partials_of(k));
     };
-    auto out = [&](int k, OocSet& S, hipStream_t s) {
-      return (slab_out(x, S.s[0], k, s) || slab_out(r, S.s[2], k, s)) ? WD_ERR_HIP : WD_OK;
+    auto out = [&](int k, OocSet& S, Moves& m) {
+      slab_out(m, x, S.s[0], k);
+      slab_out(m, r, S.s[2], k);
     };
     int rc = sweep(true, in, kern, out);
     if (rc) return rc;
@@ -453,29 +524,31 @@ struct Ooc {
   }
   // p = r + beta p
   int sweep_p_update() {
-    auto in = [&](int k, OocSet& S, hipStream_t s) {
-      return (slab_in(S.s[0], r, k, s) || slab_in(S.s[1], p, k, s)) ? WD_ERR_HIP : WD_OK;
+    auto in = [&](int k, OocSet& S, Moves& m) {
+      slab_in(m, S.s[0], r, k);
+      slab_in(m, S.s[1], p, k);
     };
     auto kern = [&](int k, OocSet& S, hipStream_t s) {
       const size_t n = (size_t)ts_of(k) * sp_plane();
       k_ooc_p_update<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(n, S.s[0], S.s[1], L.st);
     };
-    auto out = [&](int k, OocSet& S, hipStream_t s) { return slab_out(p, S.s[1], k, s); };
+    auto out = [&](int k, OocSet& S, Moves& m) { slab_out(m, p, S.s[1], k); };
     return sweep(false, in, kern, out);
   }
   // r = b' - D^+ t (p = r too when restart); ||r||^2 -> fin
   int sweep_residual(int fin, bool set_p) {
-    auto in = [&](int k, OocSet& S, hipStream_t s) {
-      return (links_in(S.U, k, s) || window_in(S.win, t, k, s) || slab_in(S.s[0], bp, k, s)) ? WD_ERR_HIP : WD_OK;
+    auto in = [&](int k, OocSet& S, Moves& m) {
+      links_in(m, S.U, k);
+      window_in(m, S.win, t, k);
+      slab_in(m, S.s[0], bp, k);
     };
     auto kern = [&](int k, OocSet& S, hipStream_t s) {
       k_ooc_residual<<<grid_of(k), kBlock, 0, s>>>(geom_of(k), gauge_of(S), win_of(S), S.s[0], S.s[1],
                                                    set_p ? S.s[2] : nullptr, diag, partials_of(k));
     };
-    auto out = [&](int k, OocSet& S, hipStream_t s) {
-      if (slab_out(r, S.s[1], k, s)) return WD_ERR_HIP;
-      if (set_p && slab_out(p, S.s[2], k, s)) return WD_ERR_HIP;
-      return WD_OK;
+    auto out = [&](int k, OocSet& S, Moves& m) {
+      slab_out(m, r, S.s[1], k);
+      if (set_p) slab_out(m, p, S.s[2], k);
     };
     int rc = sweep(true, in, kern, out);
     if (rc) return rc;
