@@ -128,7 +128,9 @@ def load(path: str | None = None) -> ctypes.CDLL:
     global _lib
     if _lib is not None:
         return _lib
-    p = path or LIB_PATH
+    # WILSON_MI355X_LIB selects another build of this library (the host
+    # sanitizer build); there is no other implementation to fall back to
+    p = path or os.environ.get("WILSON_MI355X_LIB") or LIB_PATH
     if not os.path.exists(p):
         raise RuntimeError(
             f"{p} not found: build the HIP library first (python -m paper_2001_05218_amd.build); "

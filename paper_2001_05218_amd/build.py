@@ -1,6 +1,7 @@
 """Build the HIP shared library in-tree with hipcc for gfx950.
 
     python -m paper_2001_05218_amd.build      (or __graft_entry__.build())
+    python -m paper_2001_05218_amd.build --sanitize   (host ASan/UBSan build, see SANITIZE)
 
 Every source under csrc/ is compiled to an object in csrc/_build/ (in
 parallel) and linked into paper_2001_05218_amd/libwilson_mi355x.so. The
@@ -43,33 +44,51 @@ def sources():
     return out
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+# Host-code sanitizers for the checking build (--sanitize): AddressSanitizer
+# and UndefinedBehaviorSanitizer on the host side only (device code is built
+# as usual). The result is a separate library, loaded by setting
+# WILSON_MI355X_LIB to its path and preloading the ASan runtime.
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+SAN_BUILD = os.path.join(BUILD, "sanitize")
+SAN_LIB_PATH = os.path.join(SAN_BUILD, "libwilson_mi355x_sanitize.so")
+
+
+def _compile(src: str, sanitize: bool = False) -> str:
+    out_dir = SAN_BUILD if sanitize else BUILD
+    obj = os.path.join(out_dir, os.path.basename(src) + ".o")
     cmd = [hipcc(), *COMMON, "-c", src, "-o", obj]
     cmd[1:1] = ["-x", "hip"]
     cmd += DEVICE
+    if sanitize:
+        cmd += SANITIZE
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     return obj
 
 
-def build(verbose: bool = True) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = True, sanitize: bool = False) -> str:
+    out_dir = SAN_BUILD if sanitize else BUILD
+    lib = SAN_LIB_PATH if sanitize else LIB_PATH
+    os.makedirs(out_dir, exist_ok=True)
     srcs = sources()
     jobs = min(len(srcs), int(os.environ.get("MAX_JOBS", "8")), 16)
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB_PATH + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, sanitize), srcs))
+    tmp = lib + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    if sanitize:
+        cmd += ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                "-Xarch_host", "-shared-libsan"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB_PATH)
+    os.replace(tmp, lib)
     if verbose:
-        print(f"built {LIB_PATH}", file=sys.stderr)
-    return LIB_PATH
+        print(f"built {lib}", file=sys.stderr)
+    return lib
 
 
 if __name__ == "__main__":
-    build()
+    build(sanitize="--sanitize" in sys.argv[1:])
