@@ -459,16 +459,19 @@ template <> struct PackedSpinor<P_I8> {
     }
     const float inv = (m > 0.f) ? fminf(127.0f / m, 3.4e38f) : 0.f;   // capped as for FP16
     sc = (chk == 0.f) ? m : __builtin_nanf("");
+    // q = round(v * 127 / m) in [-127, 127] (|v| <= m), rounded to nearest even:
+    // v_cvt_pk_u8_f32 rounds v * 127 / m + 128 (exact in FP32; 128 is even, so
+    // the rounding is that of v * 127 / m) into a byte lane, and flipping each
+    // byte's top bit turns the offset-binary q + 128 into two's complement q
 #pragma unroll
     for (int w = 0; w < 3; ++w) {
       uint32_t u[2] = {0u, 0u};
 #pragma unroll
-      for (int k = 0; k < 2; ++k)
+      for (int k = 0; k < 2; ++k) {
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int q = (int)rintf(fminf(fmaxf(v[8 * w + 4 * k + b] * inv, -127.f), 127.f));
-          u[k] |= ((uint32_t)q & 0xffu) << (8 * b);
-        }
+        for (int b = 0; b < 4; ++b) u[k] = __builtin_amdgcn_cvt_pk_u8_f32(fmaf(v[8 * w + 4 * k + b], inv, 128.0f), b, u[k]);
+        u[k] ^= 0x80808080u;
+      }
       d[w] = make_uint2(u[0], u[1]);
     }
   }

@@ -401,11 +401,18 @@ __global__ __launch_bounds__(kBlock) WD_TILED_OCCUPANCY void k_wilson_tiled(Geom
   }
   __shared__ TileLds<P> lds;
   uint32_t lk[8][9];
-  tile_stage<P, C12>(g, T, U, in, lds, lk);
-  __syncthreads();
-  tile_links_late<C12>(g, T, U, lk);
   float o[24];
-  tile_wilson<P, C12, DAG>(lds, lk, (float)diag, o);
+  if constexpr (P == P_I8) {
+    tile_stage<P, C12>(g, T, U, in, lds, lk, -0.5f);
+    __syncthreads();
+    tile_links_late<C12>(g, T, U, lk);
+    tile_wilson_i8<C12, DAG>(lds, lk, -2.0f * (float)diag, o);
+  } else {
+    tile_stage<P, C12>(g, T, U, in, lds, lk);
+    __syncthreads();
+    tile_links_late<C12>(g, T, U, lk);
+    tile_wilson<P, C12, DAG>(lds, lk, (float)diag, o);
+  }
   spinor_of<P>(out).store(T * kTileSites + threadIdx.x, o);
   if (fin != F_NONE) {
     double n2 = 0.0;
@@ -433,18 +440,35 @@ __global__ __launch_bounds__(kBlock) WD_TILED_OCCUPANCY void k_cg_update_tiled(G
   if (!gate_open(st, G_ITER)) return;
   __shared__ TileLds<P> lds;
   uint32_t lk[8][9];
-  tile_stage<P, C12>(g, T, U, t, lds, lk);
-  __syncthreads();
-  tile_links_late<C12>(g, T, U, lk);
-  float q[24];
-  tile_wilson<P, C12, true>(lds, lk, (float)diag, q);
   const int s = T * kTileSites + threadIdx.x;
   const float a = (float)st->alpha;
   float rv[24];
   const auto rs = spinor_of<P>(r);
-  rs.load(s, rv);
+  if constexpr (P == P_I8) {
+    // y = -alpha D^+ t straight from the hops (kappa = alpha / 2), then
+    // r = factor * (r's bytes) + y: no separate scaling of q or r
+    tile_stage<P, C12>(g, T, U, t, lds, lk, 0.5f * a);
+    __syncthreads();
+    tile_links_late<C12>(g, T, U, lk);
+    float y[24];
+    tile_wilson_i8<C12, true>(lds, lk, -2.0f * (float)diag, y);
+    uint2 dr[3];
 #pragma unroll
-  for (int i = 0; i < 24; ++i) rv[i] = fmaf(-a, q[i], rv[i]);
+    for (int w = 0; w < 3; ++w) dr[w] = rs.data[word_index(s, 3, w)];
+    const float fr = PackedSpinor<P>::raw_factor(rs.load_scale(s));
+    PackedSpinor<P>::unpack_raw(dr, rv);
+#pragma unroll
+    for (int i = 0; i < 24; ++i) rv[i] = fmaf(fr, rv[i], y[i]);
+  } else {
+    tile_stage<P, C12>(g, T, U, t, lds, lk);
+    __syncthreads();
+    tile_links_late<C12>(g, T, U, lk);
+    float q[24];
+    tile_wilson<P, C12, true>(lds, lk, (float)diag, q);
+    rs.load(s, rv);
+#pragma unroll
+    for (int i = 0; i < 24; ++i) rv[i] = fmaf(-a, q[i], rv[i]);
+  }
   typename SpinorWord<P>::T d[3];
   float sc;
   PackedSpinor<P>::pack(rv, d, sc);

@@ -62,13 +62,21 @@ __device__ __forceinline__ void stage_slot(TileLds<P>& lds, int slot, const type
   for (int w = 0; w < 3; ++w) lds.w[w][slot] = src[word_index(s, 3, w)];
   if constexpr (kScaled<P>) lds.scale[slot] = scale[s];
 }
-__device__ __forceinline__ void stage_slot(TileLds<P_I8>& lds, int slot, const uint2* src, const float* scale, int s) {
+// int8: the slot's factor is staged as kappa * scale / 127, kappa a constant
+// of the launch that the hops' sums then carry (see tile_wilson_i8).
+__device__ __forceinline__ void stage_slot(TileLds<P_I8>& lds, int slot, const uint2* src, const float* scale, int s,
+                                           float kappa) {
 #pragma unroll
   for (int w = 0; w < 3; ++w) {
     const uint2 d = src[word_index(s, 3, w)];
     lds.h[w][slot] = make_uint4(i8x2_to_h2(d.x, 0), i8x2_to_h2(d.x, 1), i8x2_to_h2(d.y, 0), i8x2_to_h2(d.y, 1));
   }
-  lds.f[slot] = scale[s] * (1.0f / 127.0f);
+  lds.f[slot] = scale[s] * (kappa * (1.0f / 127.0f));
+}
+template <int P>
+__device__ __forceinline__ void stage_slot(TileLds<P>& lds, int slot, const typename SpinorWord<P>::T* src,
+                                           const float* scale, int s, float) {
+  stage_slot(lds, slot, src, scale, s);
 }
 
 // Links are stored either as all 9 entries (18 reals) or, for SU(3) fields,
@@ -105,11 +113,11 @@ constexpr int kEarlyDirs = 2;
 // Stage the tile's spinors and halo faces; prefetch the early links of site s.
 template <int P, bool C12>
 __device__ __forceinline__ void tile_stage(const Geom& g, int T, const void* Uv, const SpinorBuf& in, TileLds<P>& lds,
-                                           uint32_t lk[8][9]) {
+                                           uint32_t lk[8][9], float kappa = 1.0f) {
   const int l = threadIdx.x;
   const int s = T * kTileSites + l;
   const typename SpinorWord<P>::T* src = static_cast<const typename SpinorWord<P>::T*>(in.data);
-  stage_slot(lds, l, src, in.scale, s);
+  stage_slot(lds, l, src, in.scale, s, kappa);
   // halo: wavefront mu stages the two mu faces
   const int mu = l >> 6;
   const int f = l & 63;
@@ -119,8 +127,8 @@ __device__ __forceinline__ void tile_stage(const Geom& g, int T, const void* Uv,
   const int sm = tile_step(g, T, b, mu, -1) * kTileSites + face_insert(f, mu, 3);
   const int slot_p = kTileSites + (2 * mu) * 64 + f;
   const int slot_m = kTileSites + (2 * mu + 1) * 64 + f;
-  stage_slot(lds, slot_p, src, in.scale, sp);
-  stage_slot(lds, slot_m, src, in.scale, sm);
+  stage_slot(lds, slot_p, src, in.scale, sp, kappa);
+  stage_slot(lds, slot_m, src, in.scale, sm, kappa);
   tile_links<C12, 0, kEarlyDirs>(g, T, Uv, lk);
 }
 
@@ -324,6 +332,21 @@ __device__ __forceinline__ float dot2(uint32_t a, uint32_t b, float c) {
   return __builtin_amdgcn_fdot2(__builtin_bit_cast(wd_f16x2, a), __builtin_bit_cast(wd_f16x2, b), c, false);
 }
 
+// a.x * b.x + a.y * b.y, and its negative, as one VOP3P instruction with an
+// inline zero addend (and negated second operand): given a zero accumulator the
+// compiler otherwise picks the two-operand form and zeroes a register first,
+// and negates results with a separate xor.
+__device__ __forceinline__ float dot2z(uint32_t a, uint32_t b) {
+  float r;
+  asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ float ndot2z(uint32_t a, uint32_t b) {
+  float r;
+  asm("v_dot2_f32_f16 %0, %1, %2, 0 neg_lo:[0,1,0] neg_hi:[0,1,0]" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
 // Written out: given the same sum as half2 vector code, the compiler builds
 // the swapped or negated first operand with separate instructions (2-3 per
 // form instead of none). v_pk_add_f16 is a plain VALU op: no wait states.
@@ -371,8 +394,8 @@ __device__ __forceinline__ void su3_third_row_h(uint32_t u[9]) {
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const int i = (k + 1) % 3, j = (k + 2) % 3;
-    const float re = dot2(u[i], c1[j], -dot2(u[j], c1[i], 0.f));   // Re(u0_i u1_j - u0_j u1_i)
-    const float im = dot2(u[j], s1[i], -dot2(u[i], s1[j], 0.f));   // -Im(u0_i u1_j - u0_j u1_i)
+    const float re = dot2(u[i], c1[j], ndot2z(u[j], c1[i]));   // Re(u0_i u1_j - u0_j u1_i)
+    const float im = dot2(u[j], s1[i], ndot2z(u[i], s1[j]));   // -Im(u0_i u1_j - u0_j u1_i)
     u[6 + k] = pack_f16x2(re, im);
   }
 }
@@ -409,9 +432,11 @@ __device__ __forceinline__ void hop_h_words(const uint32_t psi[12], float f, con
   for (int k = 0; k < 2; ++k) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      float re = 0.f, im = 0.f;
+      const int e0 = ADJ ? i : i * 3;
+      float re = dot2z(u[e0], ha[k * 3]);
+      float im = dot2z(u[e0], hb[k * 3]);
 #pragma unroll
-      for (int j = 0; j < 3; ++j) {
+      for (int j = 1; j < 3; ++j) {
         const int e = ADJ ? (j * 3 + i) : (i * 3 + j);
         re = dot2(u[e], ha[k * 3 + j], re);
         im = dot2(u[e], hb[k * 3 + j], im);
@@ -455,37 +480,47 @@ __device__ __forceinline__ void tile_hop_h(const TileLds<P_I8>& lds, const uint3
 template <int P, bool C12, bool DAG>
 __device__ __forceinline__ void tile_wilson(const TileLds<P>& lds, const uint32_t lk[8][9], float diag,
                                             float out[24]) {
+  static_assert(P != P_I8, "int8 tiles use tile_wilson_i8");
   const int l = threadIdx.x;
   float acc[24];
 #pragma unroll
   for (int i = 0; i < 24; ++i) acc[i] = 0.f;
   float c[24];
-  float dc;
-  if constexpr (P == P_I8) {
-    tile_hop_h<C12, 0, DAG>(lds, lk, l, acc);
-    tile_hop_h<C12, 1, DAG>(lds, lk, l, acc);
-    tile_hop_h<C12, 2, DAG>(lds, lk, l, acc);
-    tile_hop_h<C12, 3, DAG>(lds, lk, l, acc);
-#pragma unroll
-    for (int w = 0; w < 3; ++w) {
-      const uint4 d = lds.h[w][l];
-      const uint32_t q[4] = {d.x, d.y, d.z, d.w};
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        c[8 * w + 2 * k] = h_bits2f(q[k]);
-        c[8 * w + 2 * k + 1] = h_bits2f(q[k] >> 16);
-      }
-    }
-    dc = diag * lds.f[l];
-  } else {
-    tile_hop<P, C12, 0, DAG>(lds, lk, l, acc);
-    tile_hop<P, C12, 1, DAG>(lds, lk, l, acc);
-    tile_hop<P, C12, 2, DAG>(lds, lk, l, acc);
-    tile_hop<P, C12, 3, DAG>(lds, lk, l, acc);
-    dc = diag * tile_spinor_raw<P>(lds, l, c);
-  }
+  tile_hop<P, C12, 0, DAG>(lds, lk, l, acc);
+  tile_hop<P, C12, 1, DAG>(lds, lk, l, acc);
+  tile_hop<P, C12, 2, DAG>(lds, lk, l, acc);
+  tile_hop<P, C12, 3, DAG>(lds, lk, l, acc);
+  const float dc = diag * tile_spinor_raw<P>(lds, l, c);
 #pragma unroll
   for (int i = 0; i < 24; ++i) out[i] = fmaf(dc, c[i], -0.5f * acc[i]);
+}
+
+// int8 tiles staged with factor kappa: out = dcoef * f_l * psi(x) + kappa * sum of hops,
+// f_l the staged factor of the thread's own site. The launch chooses kappa so
+// that no per-value scaling is left: D psi is kappa = -1/2, dcoef = -2 diag;
+// -alpha D^+ t is kappa = alpha / 2, dcoef = -2 diag.
+template <bool C12, bool DAG>
+__device__ __forceinline__ void tile_wilson_i8(const TileLds<P_I8>& lds, const uint32_t lk[8][9], float dcoef,
+                                               float out[24]) {
+  const int l = threadIdx.x;
+  float acc[24];
+#pragma unroll
+  for (int i = 0; i < 24; ++i) acc[i] = 0.f;
+  tile_hop_h<C12, 0, DAG>(lds, lk, l, acc);
+  tile_hop_h<C12, 1, DAG>(lds, lk, l, acc);
+  tile_hop_h<C12, 2, DAG>(lds, lk, l, acc);
+  tile_hop_h<C12, 3, DAG>(lds, lk, l, acc);
+  const float dc = dcoef * lds.f[l];
+#pragma unroll
+  for (int w = 0; w < 3; ++w) {
+    const uint4 d = lds.h[w][l];
+    const uint32_t q[4] = {d.x, d.y, d.z, d.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      out[8 * w + 2 * k] = fmaf(dc, h_bits2f(q[k]), acc[8 * w + 2 * k]);
+      out[8 * w + 2 * k + 1] = fmaf(dc, h_bits2f(q[k] >> 16), acc[8 * w + 2 * k + 1]);
+    }
+  }
 }
 
 }  // namespace wd
