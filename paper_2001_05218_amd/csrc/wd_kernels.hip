@@ -402,11 +402,11 @@ __global__ __launch_bounds__(kBlock) WD_TILED_OCCUPANCY void k_wilson_tiled(Geom
   __shared__ TileLds<P> lds;
   uint32_t lk[8][9];
   float o[24];
-  if constexpr (P == P_I8) {
+  if constexpr (P == P_I8 || P == P_F16) {
     tile_stage<P, C12>(g, T, U, in, lds, lk, -0.5f);
     __syncthreads();
     tile_links_late<C12>(g, T, U, lk);
-    tile_wilson_i8<C12, DAG>(lds, lk, -2.0f * (float)diag, o);
+    tile_wilson_h<C12, DAG>(lds, lk, -2.0f * (float)diag, o);
   } else {
     tile_stage<P, C12>(g, T, U, in, lds, lk);
     __syncthreads();
@@ -415,10 +415,11 @@ __global__ __launch_bounds__(kBlock) WD_TILED_OCCUPANCY void k_wilson_tiled(Geom
   }
   spinor_of<P>(out).store(T * kTileSites + threadIdx.x, o);
   if (fin != F_NONE) {
-    double n2 = 0.0;
+    // the site's 24 squares summed in FP32 (relative 1e-7), the sites in FP64
+    float s2 = 0.f;
 #pragma unroll
-    for (int i = 0; i < 24; ++i) n2 += (double)o[i] * (double)o[i];
-    store_partial(n2, partials, partial_slot(T, rb));
+    for (int i = 0; i < 24; ++i) s2 = fmaf(o[i], o[i], s2);
+    store_partial((double)s2, partials, partial_slot(T, rb));
   }
 }
 
@@ -444,15 +445,15 @@ __global__ __launch_bounds__(kBlock) WD_TILED_OCCUPANCY void k_cg_update_tiled(G
   const float a = (float)st->alpha;
   float rv[24];
   const auto rs = spinor_of<P>(r);
-  if constexpr (P == P_I8) {
+  if constexpr (P == P_I8 || P == P_F16) {
     // y = -alpha D^+ t straight from the hops (kappa = alpha / 2), then
-    // r = factor * (r's bytes) + y: no separate scaling of q or r
+    // r = factor * (r's stored numbers) + y: no separate scaling of q or r
     tile_stage<P, C12>(g, T, U, t, lds, lk, 0.5f * a);
     __syncthreads();
     tile_links_late<C12>(g, T, U, lk);
     float y[24];
-    tile_wilson_i8<C12, true>(lds, lk, -2.0f * (float)diag, y);
-    uint2 dr[3];
+    tile_wilson_h<C12, true>(lds, lk, -2.0f * (float)diag, y);
+    typename SpinorWord<P>::T dr[3];
 #pragma unroll
     for (int w = 0; w < 3; ++w) dr[w] = rs.data[word_index(s, 3, w)];
     const float fr = PackedSpinor<P>::raw_factor(rs.load_scale(s));
@@ -485,6 +486,17 @@ __global__ __launch_bounds__(kBlock) WD_TILED_OCCUPANCY void k_cg_update_tiled(G
     }
     const double f = (double)PackedSpinor<P>::raw_factor(sc);
     n2 = f * f * (double)q2;
+  } else if constexpr (P == P_F16) {
+    // scale^2 times the sum of the stored halves' squares (exact products, FP32 sums)
+    float h2 = 0.f;
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+      h2 = dot2(d[w].x, d[w].x, h2);
+      h2 = dot2(d[w].y, d[w].y, h2);
+      h2 = dot2(d[w].z, d[w].z, h2);
+      h2 = dot2(d[w].w, d[w].w, h2);
+    }
+    n2 = (double)sc * (double)sc * (double)h2;
   } else {
     PackedSpinor<P>::unpack(d, sc, rv);
 #pragma unroll

@@ -46,13 +46,16 @@ struct TileLds {
   float scale[kTileSlots];
 };
 
-// int8 storage: staged already converted, 12 half2 words (one complex each,
-// index spin * 3 + colour) per slot, and the slot's value factor scale / 127.
-template <>
-struct TileLds<P_I8> {
+// FP16 and int8 storage: 12 half2 words (one complex each, index
+// spin * 3 + colour) per slot and the slot's value factor (FP16: the site's
+// scale; int8: scale / 127, the bytes converted to half when staged), so that
+// both run the same packed-half hops.
+struct HalfTile {
   uint4 h[3][kTileSlots];
   float f[kTileSlots];
 };
+template <> struct TileLds<P_F16> : HalfTile {};
+template <> struct TileLds<P_I8> : HalfTile {};
 
 // Store one site's spinor words (and scale) into an LDS slot.
 template <int P>
@@ -62,8 +65,14 @@ __device__ __forceinline__ void stage_slot(TileLds<P>& lds, int slot, const type
   for (int w = 0; w < 3; ++w) lds.w[w][slot] = src[word_index(s, 3, w)];
   if constexpr (kScaled<P>) lds.scale[slot] = scale[s];
 }
-// int8: the slot's factor is staged as kappa * scale / 127, kappa a constant
-// of the launch that the hops' sums then carry (see tile_wilson_i8).
+// FP16 and int8: the slot's factor is staged times kappa, a constant of the
+// launch that the hops' sums then carry (see tile_wilson_h).
+__device__ __forceinline__ void stage_slot(TileLds<P_F16>& lds, int slot, const uint4* src, const float* scale, int s,
+                                           float kappa) {
+#pragma unroll
+  for (int w = 0; w < 3; ++w) lds.h[w][slot] = src[word_index(s, 3, w)];
+  lds.f[slot] = scale[s] * kappa;
+}
 __device__ __forceinline__ void stage_slot(TileLds<P_I8>& lds, int slot, const uint2* src, const float* scale, int s,
                                            float kappa) {
 #pragma unroll
@@ -448,9 +457,9 @@ __device__ __forceinline__ void hop_h_words(const uint32_t psi[12], float f, con
   reconstruct_fma<MU, S>(acc, w, f);
 }
 
-// The same for a staged int8 slot.
+// The same for a staged FP16 or int8 slot.
 template <int MU, int S, bool ADJ, bool C12>
-__device__ __forceinline__ void hop_h(const TileLds<P_I8>& lds, int slot, const uint32_t raw[9], float acc[24]) {
+__device__ __forceinline__ void hop_h(const HalfTile& lds, int slot, const uint32_t raw[9], float acc[24]) {
   uint32_t psi[12];
 #pragma unroll
   for (int w = 0; w < 3; ++w) {
@@ -464,7 +473,7 @@ __device__ __forceinline__ void hop_h(const TileLds<P_I8>& lds, int slot, const 
 }
 
 template <bool C12, int MU, bool DAG>
-__device__ __forceinline__ void tile_hop_h(const TileLds<P_I8>& lds, const uint32_t lk[8][9], int l, float acc[24]) {
+__device__ __forceinline__ void tile_hop_h(const HalfTile& lds, const uint32_t lk[8][9], int l, float acc[24]) {
   constexpr int SF = DAG ? +1 : -1;
   constexpr int ls = 1 << (2 * MU);
   const int lm = (l >> (2 * MU)) & 3;
@@ -480,7 +489,7 @@ __device__ __forceinline__ void tile_hop_h(const TileLds<P_I8>& lds, const uint3
 template <int P, bool C12, bool DAG>
 __device__ __forceinline__ void tile_wilson(const TileLds<P>& lds, const uint32_t lk[8][9], float diag,
                                             float out[24]) {
-  static_assert(P != P_I8, "int8 tiles use tile_wilson_i8");
+  static_assert(P != P_I8 && P != P_F16, "FP16 and int8 tiles use tile_wilson_h");
   const int l = threadIdx.x;
   float acc[24];
 #pragma unroll
@@ -495,13 +504,16 @@ __device__ __forceinline__ void tile_wilson(const TileLds<P>& lds, const uint32_
   for (int i = 0; i < 24; ++i) out[i] = fmaf(dc, c[i], -0.5f * acc[i]);
 }
 
-// int8 tiles staged with factor kappa: out = dcoef * f_l * psi(x) + kappa * sum of hops,
-// f_l the staged factor of the thread's own site. The launch chooses kappa so
-// that no per-value scaling is left: D psi is kappa = -1/2, dcoef = -2 diag;
-// -alpha D^+ t is kappa = alpha / 2, dcoef = -2 diag.
+// FP16 and int8 tiles staged with factor kappa: out = dcoef * f_l * psi(x) +
+// kappa * sum of hops, f_l the staged factor of the thread's own site. The
+// launch chooses kappa so that no per-value scaling is left: D psi is
+// kappa = -1/2, dcoef = -2 diag; -alpha D^+ t is kappa = alpha / 2, dcoef = -2 diag.
+// The hops run in packed half precision with FP32 dot products: exact for
+// int8 data; for FP16 data the spin projection rounds to half once (relative
+// 2^-11, the resolution the values are stored with).
 template <bool C12, bool DAG>
-__device__ __forceinline__ void tile_wilson_i8(const TileLds<P_I8>& lds, const uint32_t lk[8][9], float dcoef,
-                                               float out[24]) {
+__device__ __forceinline__ void tile_wilson_h(const HalfTile& lds, const uint32_t lk[8][9], float dcoef,
+                                              float out[24]) {
   const int l = threadIdx.x;
   float acc[24];
 #pragma unroll
