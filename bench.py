@@ -223,7 +223,12 @@ def cpu_plan_part(name, full):
     if full:
         log(f"{name}: full oracle solve")
         t = time.perf_counter()
-        _, info = oracle.cgnr(U, b, mass, tol=TOL, max_iter=20000)
+
+        def progress(k, rel):
+            if k % 10 == 0:
+                log(f"{name}: oracle CG iteration {k}, relative residual {rel:.2e}, "
+                    f"{time.perf_counter() - t:.0f} s")
+        _, info = oracle.cgnr(U, b, mass, tol=TOL, max_iter=20000, progress=progress)
         out.update({"solve_seconds": time.perf_counter() - t, "iterations": info["iterations"],
                     "true_rel_res": info["true_rel_res"]})
     print(json.dumps({name: out}), flush=True)
@@ -237,14 +242,14 @@ def run_cpu_plan():
     procs = {}
     for name in WORKLOADS:
         cmd = [sys.executable, os.path.abspath(__file__), "--cpu-plan-part", name]
-        procs[name] = subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env)
+        procs[name] = subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=None, text=True, env=env)
         if name not in FULL_SOLVES:   # the large ones alone, so that they do not share memory bandwidth
             procs[name].wait()
     res = {}
     for name, pr in procs.items():
-        outp, errp = pr.communicate()
+        outp, _ = pr.communicate()
         if pr.returncode != 0:
-            raise RuntimeError(errp[-2000:])
+            raise RuntimeError(f"{name}: oracle timing failed (exit {pr.returncode})")
         res.update(json.loads(outp.strip().splitlines()[-1]))
     print(json.dumps({"cpu_oracle_plan": res, "cores_per_run": 1, "host_logical_cpus": os.cpu_count(),
                       "threads_env": {k: env[k] for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS",
@@ -448,20 +453,23 @@ def stream_ceiling(dev, gib=8, reps=5):
 
 def ooc_pcie_bytes(dims, ts, nslab, iters):
     """Bytes one out-of-core solve moves each way: per slab k of t_k planes, an
-    iteration copies in the links of t_k + 1 planes twice (t = D p; D^+ t) and
-    t_k + 2, t_k + 2 + 3 t_k and 2 t_k spinor planes; it copies out t_k, 2 t_k
-    and t_k planes (t; x, r; p). Set-up (D^+ b; r = p = b'; x = 0) and the
-    final residual (D x; b' - D^+ t) are added once."""
+    iteration copies in the links of t_k + 1 planes twice (t = D p; D^+ t), the
+    r, p and t windows (t_k + 2 planes each), x and r (t_k planes each); it
+    copies out p, t, x and r (t_k planes each). Set-up (D^+ b; b' = r = p; x = 0),
+    the last deferred x update and the final residual (D x; b' - D^+ t) are
+    added once."""
     lx, ly, lz, lt = dims
     plane = lx * ly * lz
     sp, lk = 192 * plane, 4 * 144 * plane
     h2d = d2h = 0
     for k in range(nslab):
         t = min(ts, lt - k * ts)
-        h2d += iters * (2 * (t + 1) * lk + (t + 2 + t + 2 + 3 * t + 2 * t) * sp)
-        d2h += iters * (t + 2 * t + t) * sp
-        h2d += (t + 1) * lk + (t + 2) * sp + (t + 1) * lk + (t + 2) * sp + (t + 1) * lk + (t + 2 + t) * sp
-        d2h += 4 * t * sp + t * sp + 2 * t * sp
+        h2d += iters * (2 * (t + 1) * lk + (3 * (t + 2) + 2 * t) * sp)
+        d2h += iters * 4 * t * sp
+        h2d += (t + 1) * lk + (t + 2) * sp          # set-up
+        h2d += 2 * t * sp                           # last x update
+        h2d += 2 * ((t + 1) * lk + (t + 2) * sp) + t * sp   # D x; b' - D^+ t
+        d2h += 4 * t * sp + t * sp + t * sp + 2 * t * sp
     return h2d, d2h
 
 

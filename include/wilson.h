@@ -268,13 +268,15 @@ int wilson_force(const wd_lattice* lat, const void* a, const void* b, double coe
  * (copies in, kernels, copies out) and two device buffer sets, so that copies
  * of neighbouring slabs overlap the kernels. The copies are kernels that read
  * and write the pinned host memory in place (one launch per slab and
- * direction). One iteration moves about 2.5 KB per site to the device and
- * 0.8 KB back. */
+ * direction). One iteration is two sweeps (t = D p with the search-direction
+ * and deferred solution updates; r -= alpha D^+ t) and moves about 2.1 KB per
+ * site to the device and 0.8 KB back (more for slabs of few planes, whose
+ * halo planes are a larger share). */
 
 /* Workspace of cg_solve_ooc for slabs of slab_planes time planes
  * (1 <= slab_planes <= Lt) and a residual history of history_len entries:
- * *device_bytes (device memory) and *host_bytes (pinned host memory: four
- * FP64 spinor fields, b' r p t). Either pointer may be NULL. Returns WD_OK or
+ * *device_bytes (device memory) and *host_bytes (pinned host memory: five
+ * FP64 spinor fields, b', r, two search directions, t). Either pointer may be NULL. Returns WD_OK or
  * WD_ERR_INVALID. */
 int wd_ooc_workspace_bytes(const wd_lattice* lat, int32_t slab_planes, int32_t history_len, size_t* device_bytes,
                            size_t* host_bytes);

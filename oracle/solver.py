@@ -30,12 +30,14 @@ def _norm2(a: np.ndarray) -> float:
     return float(np.vdot(a, a).real)
 
 
-def cgnr(U, b, mass, tol=1e-10, max_iter=10000, rhs="source", x0=None, history=False):
+def cgnr(U, b, mass, tol=1e-10, max_iter=10000, rhs="source", x0=None, history=False, progress=None):
     """Solve D^dagger D x = D^dagger b (rhs="source") or D^dagger D x = b (rhs="normal").
 
     Returns (x, info) where info holds the iteration count, the iterated and
     the recomputed ("true") relative residuals and, if asked, the iterated
-    relative residual after every step.
+    relative residual after every step. ``progress(k, rel)``, if given, is
+    called after every step (for long timed runs; it does not touch the
+    arithmetic).
     """
     if rhs == "source":
         bp = wilson_Ddag(U, b, mass)
@@ -64,6 +66,8 @@ def cgnr(U, b, mass, tol=1e-10, max_iter=10000, rhs="source", x0=None, history=F
         rel = np.sqrt(rho_new) / bnorm
         if history:
             hist.append(rel)
+        if progress is not None:
+            progress(k, rel)
         beta = rho_new / rho
         p = r + beta * p
         rho = rho_new

@@ -12,13 +12,16 @@
 // sides of a slab; the window copied in holds them (a lower and an upper halo
 // plane, periodic in t), and the links of the plane below.
 //
-// One CGNR iteration is three sweeps (with b' = D^+ b or b, M = D^+ D):
-//   S1  t = D p              in: U, p window    out: t      ||t||^2 -> alpha
-//   S2  q = D^+ t; x += alpha p; r -= alpha q
-//                            in: U, t window, x, p, r      out: x, r     ||r||^2 -> beta
-//   S3  p = r + beta p       in: r, p           out: p
-// The scalars never leave the device (finalize kernels on the kernel stream);
-// the host reads the state once per iteration, after S3 has been queued.
+// One CGNR iteration k is two sweeps (b' = D^+ b or b, M = D^+ D):
+//   S1  p_k = r_k + beta_{k-1} p_{k-1} (on the whole window), t = D p_k,
+//       x += alpha_{k-1} p_{k-1}       in: U, r and p windows, x
+//                                      out: p_k, t, x     ||t||^2 -> alpha_k
+//   S2  r_{k+1} = r_k - alpha_k D^+ t  in: U, t window, r  out: r  ||r||^2 -> beta_k
+// The solution update lags one iteration behind (x is not needed by the
+// recurrences): S1 applies the previous step's alpha p while it holds that p,
+// and a last short sweep applies the final one. The scalars never leave the
+// device (finalize kernels on the kernel stream); the host reads the state
+// once per iteration.
 // Each sweep may start copying in as soon as the slabs it reads have been
 // written back by the sweep before: a sweep whose input is a window starts one
 // slab later than the sweep before it (its first slab then needs only slabs
@@ -31,6 +34,7 @@
 #include <cmath>
 #include <cstdio>
 #include <mutex>
+#include <utility>
 #include <vector>
 
 #include "wd_dslash.hpp"
@@ -94,36 +98,6 @@ __global__ __launch_bounds__(kBlock) void k_ooc_apply(SlabGeom g, CanonGauge U, 
   store_partial(n2, partials);
 }
 
-// q = D^+ t; x += alpha p; r -= alpha q; ||r||^2.
-__global__ __launch_bounds__(kBlock) void k_ooc_update(SlabGeom g, CanonGauge U, CanonSpinor t,
-                                                       double2* __restrict__ x, const double2* __restrict__ p,
-                                                       double2* __restrict__ r, double diag,
-                                                       const SolverState* __restrict__ st,
-                                                       double* __restrict__ partials) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  double n2 = 0.0;
-  if (i < g.ts * g.plane) {
-    const int w = g.plane + i;
-    double q[24];
-    wilson_site<true>(U, t, w, slab_neighbours(g, w), diag, q);
-    const double a = st->alpha;
-#pragma unroll
-    for (int k = 0; k < 12; ++k) {
-      const size_t e = (size_t)i * 12 + k;
-      const double2 pv = p[e];
-      double2 xv = x[e], rv = r[e];
-      xv.x = fma(a, pv.x, xv.x);
-      xv.y = fma(a, pv.y, xv.y);
-      rv.x = fma(-a, q[2 * k], rv.x);
-      rv.y = fma(-a, q[2 * k + 1], rv.y);
-      x[e] = xv;
-      r[e] = rv;
-      n2 += rv.x * rv.x + rv.y * rv.y;
-    }
-  }
-  store_partial(n2, partials);
-}
-
 // r = b' - D^+ t (and p = r when p is given); ||r||^2.
 __global__ __launch_bounds__(kBlock) void k_ooc_residual(SlabGeom g, CanonGauge U, CanonSpinor t,
                                                          const double2* __restrict__ bp, double2* __restrict__ r,
@@ -148,18 +122,71 @@ __global__ __launch_bounds__(kBlock) void k_ooc_residual(SlabGeom g, CanonGauge 
   store_partial(n2, partials);
 }
 
-// p = r + beta p over n complex numbers.
-__global__ __launch_bounds__(kBlock) void k_ooc_p_update(size_t n, const double2* __restrict__ r,
-                                                         double2* __restrict__ p,
-                                                         const SolverState* __restrict__ st) {
+// The search direction over a whole window (ts + 2 planes): p = r + beta p.
+// On the slab's own planes (window planes 1 .. ts) also x += alpha p_old, the
+// deferred solution update of the previous iteration.
+__global__ __launch_bounds__(kBlock) void k_ooc_pwin(size_t n_win, size_t lo, size_t hi, const double2* __restrict__ r,
+                                                     double2* __restrict__ p, double2* __restrict__ x,
+                                                     const SolverState* __restrict__ st) {
   const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
-  if (e >= n) return;
+  if (e >= n_win) return;
   const double beta = st->beta;
   const double2 rv = r[e];
-  double2 pv = p[e];
-  pv.x = fma(beta, pv.x, rv.x);
-  pv.y = fma(beta, pv.y, rv.y);
-  p[e] = pv;
+  const double2 po = p[e];
+  if (e >= lo && e < hi) {
+    const double alpha = st->alpha;
+    double2 xv = x[e - lo];
+    xv.x = fma(alpha, po.x, xv.x);
+    xv.y = fma(alpha, po.y, xv.y);
+    x[e - lo] = xv;
+  }
+  p[e] = make_double2(fma(beta, po.x, rv.x), fma(beta, po.y, rv.y));
+}
+
+// x += alpha p over n complex numbers (the last deferred solution update).
+__global__ __launch_bounds__(kBlock) void k_ooc_axpy(size_t n, double2* __restrict__ x, const double2* __restrict__ p,
+                                                     const SolverState* __restrict__ st) {
+  const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= n) return;
+  const double alpha = st->alpha;
+  const double2 pv = p[e];
+  double2 xv = x[e];
+  xv.x = fma(alpha, pv.x, xv.x);
+  xv.y = fma(alpha, pv.y, xv.y);
+  x[e] = xv;
+}
+
+// alpha = beta = 0: the next S1 starts a new Krylov space (p = r) and adds
+// nothing to x.
+__global__ void k_ooc_reset_ab(SolverState* st) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  st->alpha = 0.0;
+  st->beta = 0.0;
+}
+
+// r -= alpha D^+ t; ||r||^2.
+__global__ __launch_bounds__(kBlock) void k_ooc_rupdate(SlabGeom g, CanonGauge U, CanonSpinor t,
+                                                        double2* __restrict__ r, double diag,
+                                                        const SolverState* __restrict__ st,
+                                                        double* __restrict__ partials) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  double n2 = 0.0;
+  if (i < g.ts * g.plane) {
+    const int w = g.plane + i;
+    double q[24];
+    wilson_site<true>(U, t, w, slab_neighbours(g, w), diag, q);
+    const double a = st->alpha;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const size_t e = (size_t)i * 12 + k;
+      double2 rv = r[e];
+      rv.x = fma(-a, q[2 * k], rv.x);
+      rv.y = fma(-a, q[2 * k + 1], rv.y);
+      r[e] = rv;
+      n2 += rv.x * rv.x + rv.y * rv.y;
+    }
+  }
+  store_partial(n2, partials);
 }
 
 // ||v||^2 of n sites.
@@ -225,6 +252,7 @@ size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 struct OocSet {
   double2* U;      // 4 x (ts + 1) planes of links (window planes 0 .. ts)
   double2* win;    // ts + 2 planes of a spinor (window)
+  double2* win2;   // a second window
   double2* s[3];   // ts planes each
 };
 
@@ -254,6 +282,7 @@ OocLayout ooc_layout(void* base, int plane, int T, int ts, int hist_len) {
   for (int j = 0; j < 2; ++j) {
     L.set[j].U = static_cast<double2*>(take(4 * (size_t)(ts + 1) * plane * kLinkSite));
     L.set[j].win = static_cast<double2*>(take((size_t)(ts + 2) * plane * kSpinorSite));
+    L.set[j].win2 = static_cast<double2*>(take((size_t)(ts + 2) * plane * kSpinorSite));
     for (int k = 0; k < 3; ++k) L.set[j].s[k] = static_cast<double2*>(take((size_t)ts * plane * kSpinorSite));
   }
   L.bytes = off;
@@ -311,7 +340,10 @@ struct Ooc {
   const double2* U = nullptr;   // (4, T, plane, 9)
   const double2* b = nullptr;
   double2* x = nullptr;
-  double2 *bp = nullptr, *r = nullptr, *p = nullptr, *t = nullptr;
+  // host vectors; the search direction is double-buffered: S1 reads p (its
+  // window's halo planes belong to neighbouring slabs) and writes p_next, so
+  // that no slab's new p can overwrite a plane another slab has yet to read
+  double2 *bp = nullptr, *r = nullptr, *p = nullptr, *p_next = nullptr, *t = nullptr;
   // device
   OocLayout L{};
   OocDevice* dev = nullptr;
@@ -500,39 +532,60 @@ struct Ooc {
     if (fin != F_NONE) finalize(fin);
     return WD_OK;
   }
-  // q = D^+ t; x += alpha p; r -= alpha q; ||r||^2 -> beta
-  int sweep_update() {
+  // S1: p = r + beta p on the window, t = D p, x += alpha p_old; ||t||^2 -> alpha
+  int sweep_s1() {
+    auto in = [&](int k, OocSet& S, Moves& m) {
+      links_in(m, S.U, k);
+      window_in(m, S.win2, r, k);
+      window_in(m, S.win, p, k);
+      slab_in(m, S.s[0], x, k);
+    };
+    auto kern = [&](int k, OocSet& S, hipStream_t s) {
+      const size_t n_win = (size_t)(ts_of(k) + 2) * sp_plane();
+      k_ooc_pwin<<<(unsigned)((n_win + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+          n_win, sp_plane(), (size_t)(ts_of(k) + 1) * sp_plane(), S.win2, S.win, S.s[0], L.st);
+      k_ooc_apply<false><<<grid_of(k), kBlock, 0, s>>>(geom_of(k), gauge_of(S), win_of(S), S.s[1], diag,
+                                                       partials_of(k));
+    };
+    auto out = [&](int k, OocSet& S, Moves& m) {
+      slab_out(m, p_next, S.win + sp_plane(), k);   // the window's own planes
+      slab_out(m, t, S.s[1], k);
+      slab_out(m, x, S.s[0], k);
+    };
+    int rc = sweep(true, in, kern, out);
+    if (rc) return rc;
+    std::swap(p, p_next);
+    finalize(F_ALPHA);
+    return WD_OK;
+  }
+  // S2: r -= alpha D^+ t; ||r||^2 -> beta
+  int sweep_s2() {
     auto in = [&](int k, OocSet& S, Moves& m) {
       links_in(m, S.U, k);
       window_in(m, S.win, t, k);
-      slab_in(m, S.s[0], x, k);
-      slab_in(m, S.s[1], p, k);
-      slab_in(m, S.s[2], r, k);
+      slab_in(m, S.s[0], r, k);
     };
     auto kern = [&](int k, OocSet& S, hipStream_t s) {
-      k_ooc_update<<<grid_of(k), kBlock, 0, s>>>(geom_of(k), gauge_of(S), win_of(S), S.s[0], S.s[1], S.s[2], diag,
-                                                 L.st, partials_of(k));
+      k_ooc_rupdate<<<grid_of(k), kBlock, 0, s>>>(geom_of(k), gauge_of(S), win_of(S), S.s[0], diag, L.st,
+                                                  partials_of(k));
     };
-    auto out = [&](int k, OocSet& S, Moves& m) {
-      slab_out(m, x, S.s[0], k);
-      slab_out(m, r, S.s[2], k);
-    };
+    auto out = [&](int k, OocSet& S, Moves& m) { slab_out(m, r, S.s[0], k); };
     int rc = sweep(true, in, kern, out);
     if (rc) return rc;
     finalize(F_BETA);
     return WD_OK;
   }
-  // p = r + beta p
-  int sweep_p_update() {
+  // the deferred x += alpha p of the last iteration
+  int sweep_x_update() {
     auto in = [&](int k, OocSet& S, Moves& m) {
-      slab_in(m, S.s[0], r, k);
+      slab_in(m, S.s[0], x, k);
       slab_in(m, S.s[1], p, k);
     };
     auto kern = [&](int k, OocSet& S, hipStream_t s) {
       const size_t n = (size_t)ts_of(k) * sp_plane();
-      k_ooc_p_update<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(n, S.s[0], S.s[1], L.st);
+      k_ooc_axpy<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(n, S.s[0], S.s[1], L.st);
     };
-    auto out = [&](int k, OocSet& S, Moves& m) { slab_out(m, p, S.s[1], k); };
+    auto out = [&](int k, OocSet& S, Moves& m) { slab_out(m, x, S.s[0], k); };
     return sweep(false, in, kern, out);
   }
   // r = b' - D^+ t (p = r too when restart); ||r||^2 -> fin
@@ -576,7 +629,7 @@ size_t ooc_device_bytes(const int L[4], int slab_planes, int hist_len) {
 }
 
 size_t ooc_host_bytes(const int L[4]) {
-  return 4 * (size_t)L[0] * L[1] * L[2] * L[3] * kSpinorSite;
+  return 5 * (size_t)L[0] * L[1] * L[2] * L[3] * kSpinorSite;   // b', r, p, p_next, t
 }
 
 int ooc_slab_planes(const int L[4], size_t device_bytes, int hist_len) {
@@ -618,7 +671,8 @@ int ooc_solve(const int Ldims[4], double mass, const void* U, const void* b, voi
   o.bp = hw;
   o.r = hw + V * 12;
   o.p = hw + 2 * V * 12;
-  o.t = hw + 3 * V * 12;
+  o.p_next = hw + 3 * V * 12;
+  o.t = hw + 4 * V * 12;
   o.L = ooc_layout(dev_ws, o.plane, o.T, o.ts, p->history_len);
   int rc = ooc_device(&o.dev, err, errlen);
   if (rc) return rc;
@@ -667,21 +721,27 @@ int ooc_solve(const int Ldims[4], double mass, const void* U, const void* b, voi
     SolverState st{};
     if ((r2 = o.post_state()) || (r2 = o.wait_state(&st))) return r2;
     int restarts = 0;
+    // alpha = beta = 0 (from the state's initialisation): the first S1 sets
+    // p = r and adds nothing to x
+    bool pending_x = false;   // x lacks the last alpha p
     while (st.status == 0 && st.iter < p->max_iter) {
-      if ((r2 = o.sweep_D(o.p, F_ALPHA)) || (r2 = o.sweep_update())) return r2;
-      if ((r2 = o.post_state())) return r2;
-      if ((r2 = o.sweep_p_update())) return r2;   // queued before the host looks
-      if ((r2 = o.wait_state(&st))) return r2;
+      if ((r2 = o.sweep_s1()) || (r2 = o.sweep_s2())) return r2;
+      pending_x = true;
+      if ((r2 = o.post_state()) || (r2 = o.wait_state(&st))) return r2;
       if (st.status == 1) {
-        // confirm with the residual recomputed from x
+        // complete x, then confirm with the residual recomputed from it
+        if ((r2 = o.sweep_x_update())) return r2;
+        pending_x = false;
         if ((r2 = o.sweep_D(o.x, F_NONE)) || (r2 = o.sweep_residual(F_TRUE, true))) return r2;
         if ((r2 = o.post_state()) || (r2 = o.wait_state(&st))) return r2;
         if (st.rho_true <= st.stop2 || st.iter >= p->max_iter || restarts >= 5) break;
         ++restarts;   // the recurrence drifted: continue from the recomputed residual (r = p = it)
         launch_restart(o.L.st, D.comp);
+        k_ooc_reset_ab<<<1, 64, 0, D.comp>>>(o.L.st);
         if ((r2 = o.post_state()) || (r2 = o.wait_state(&st))) return r2;
       }
     }
+    if (pending_x && st.status >= 0 && (r2 = o.sweep_x_update())) return r2;
     if (st.status == 0 || (st.status == 1 && st.rho_true > st.stop2)) {
       // stopped by max_iter: the true residual of the last iterate
       if ((r2 = o.sweep_D(o.x, F_NONE)) || (r2 = o.sweep_residual(F_TRUE, false))) return r2;

@@ -35,7 +35,7 @@ def test_workspace_sizes_grow_with_slab_thickness():
     dims = (8, 8, 8, 16)
     d1, h1 = wd.ooc_workspace_bytes(dims, 1)
     d2, h2 = wd.ooc_workspace_bytes(dims, 2)
-    assert d2 > d1 and h1 == h2 == 4 * 8 * 8 * 8 * 16 * 192
+    assert d2 > d1 and h1 == h2 == 5 * 8 * 8 * 8 * 16 * 192
 
 
 def test_config0_matches_oracle_cg_history():

@@ -248,7 +248,7 @@ def test_ooc_workspace_sizes(lib):
     for ts, d in zip((1, 2, 4), dev):
         assert lib.wd_ooc_workspace_bytes(_lat(dims), ts, 0, ctypes.byref(d), ctypes.byref(host)) == 0
     assert dev[0].value < dev[1].value < dev[2].value
-    assert host.value == 4 * 8 * 8 * 8 * 16 * 192          # b', r, p, t in FP64
+    assert host.value == 5 * 8 * 8 * 8 * 16 * 192          # b', r, two p, t in FP64
     # two buffer sets of 4 (ts + 1) link planes and 3 ts + ts + 2 spinor planes,
     # so one more plane per slab costs at least 2 (4 x 144 + 4 x 192) B per site
     plane = 8 * 8 * 8
