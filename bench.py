@@ -134,6 +134,11 @@ def parse():
                     help="time the FP64 oracle on the host (per D and per CG iteration on the five workloads, full "
                          "solves on the three small ones) and print one JSON line; no GPU is used")
     ap.add_argument("--cpu-plan-part", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--summarize-trace", default=None, metavar="DIR",
+                    help="print a markdown kernel-time table from a rocprofv3 --kernel-trace output directory")
+    ap.add_argument("--summarize-traffic", nargs=2, default=None, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/traffic_*.txt from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) "
+                         "of this benchmark, calibrated by its 8 GiB streaming copy")
     return ap.parse_args()
 
 
@@ -530,8 +535,130 @@ def bench_ooc(dev, budget=64 << 20):
     return out
 
 
+# ------------------------------------------------ rocprofv3 output summaries
+
+def _rocprof_rows(directory, suffix):
+    import csv
+    import glob
+    rows = []
+    for path in sorted(glob.glob(os.path.join(directory, "**", f"*{suffix}"), recursive=True)):
+        with open(path) as f:
+            rows.extend(csv.DictReader(f))
+    if not rows:
+        raise SystemExit(f"no *{suffix} under {directory}")
+    return rows
+
+
+def _short_name(name):
+    name = name.replace("void ", "")
+    if name.startswith("wd::"):
+        name = name[4:]
+    depth, out = 0, []
+    for ch in name:   # drop the argument list, keep template arguments
+        if ch == "(" and depth == 0:
+            break
+        depth += ch == "<"
+        depth -= ch == ">"
+        out.append(ch)
+    return "".join(out).strip()
+
+
+def _working(durations):
+    """Launches that did work: the solvers enqueue iterations and reliable-update
+    slots ahead of their convergence test, and a launch whose gate is closed
+    exits within microseconds; keep those longer than 10 us and than a fifth of
+    the longest."""
+    top = max(durations)
+    return [d for d in durations if d > 10e3 and d > 0.2 * top] or durations
+
+
+def summarize_trace(directory):
+    rows = _rocprof_rows(directory, "kernel_trace.csv")
+    per = {}
+    for r in rows:
+        per.setdefault(_short_name(r["Kernel_Name"]), []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    total = sum(sum(v) for v in per.values())
+    print("name | calls | working calls | average us (working) | total ms | % of GPU time")
+    for name, d in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+        w = _working(d)
+        print(f"{name} | {len(d)} | {len(w)} | {sum(w) / len(w) / 1e3:.1f} | {sum(d) / 1e6:.1f} | "
+              f"{100.0 * sum(d) / total:.1f}")
+
+
+# kernels whose HBM traffic is stored: label -> (kernel name, algorithmic bytes per site)
+TRAFFIC_KERNELS = {
+    "k_cg_update_tiled_i8_rows2": ("k_cg_update_tiled<4, true>", loop_kernel_bytes("i8", True)["update"]),
+    "k_wilson_tiled_i8_rows2": ("k_wilson_tiled<4, true, false>", loop_kernel_bytes("i8", True)["D"]),
+    "k_cg_update_tiled_f16_rows2": ("k_cg_update_tiled<3, true>", loop_kernel_bytes("f16", True)["update"]),
+    "k_wilson_tiled_f16_rows2": ("k_wilson_tiled<3, true, false>", loop_kernel_bytes("f16", True)["D"]),
+    "k_wilson_packed_f64": ("k_wilson_packed<0, false, true>", loop_kernel_bytes("f64")["D"]),
+    "k_cg_update_f64": ("k_cg_update<0, 0, true, true>", loop_kernel_bytes("f64")["update"]),
+}
+
+
+def summarize_traffic(fetch_dir, write_dir, dims=DIMS):
+    """Per-launch FETCH_SIZE and WRITE_SIZE (KiB) of the stored kernels, each
+    scaled by what the counter reads for the benchmark's 8 GiB streaming copy
+    (k_stream_copy: bytes read = bytes written = 8 GiB, far beyond the 256 MiB
+    Infinity Cache), means over the launches that did work."""
+    V = int(np.prod(dims))
+    reads = {}
+    for directory, counter in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
+        per = {}
+        for r in _rocprof_rows(directory, "counter_collection.csv"):
+            if r["Counter_Name"] != counter:
+                continue
+            per.setdefault(_short_name(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+        reads[counter] = per
+    copy_kib = (8 << 30) / 1024
+    scale = {c: copy_kib / float(np.mean(reads[c]["k_stream_copy"])) for c in reads}
+    src = "cd /tmp && TMPDIR=/tmp timeout -s KILL 300 rocprofv3 --pmc {c} -d $R/gpurun_out/pmc_{c} -o p " \
+          "--output-format csv -- python3 $R/bench.py --steps 1 --warmup 1 --inner i8 --fp64-steps 1 " \
+          "--dslash-reps 20 --no-cpu-baseline --no-other-rows"
+    for label, (kname, bps) in TRAFFIC_KERNELS.items():
+        if kname not in reads["FETCH_SIZE"] or kname not in reads["WRITE_SIZE"]:
+            continue
+        f = float(np.mean(_working(reads["FETCH_SIZE"][kname])))
+        w = float(np.mean(_working(reads["WRITE_SIZE"][kname])))
+        traffic = (f * scale["FETCH_SIZE"] + w * scale["WRITE_SIZE"]) * 1024
+        alg = bps * V
+        lines = [
+            f"# HBM traffic of {label} on {'x'.join(map(str, dims))} (one launch = {V} sites)",
+            f"# kernel: {kname}",
+            "# Commands (R = repository root on the GPU box):",
+            "#   " + src.format(c="FETCH_SIZE"),
+            "#   " + src.format(c="WRITE_SIZE"),
+            f"#   python3 bench.py --summarize-traffic $R/gpurun_out/pmc_FETCH_SIZE $R/gpurun_out/pmc_WRITE_SIZE",
+            f"# Calibration, same runs: the 8 GiB streaming copy k_stream_copy reads FETCH_SIZE = "
+            f"{float(np.mean(reads['FETCH_SIZE']['k_stream_copy'])):.1f} KiB and WRITE_SIZE = "
+            f"{float(np.mean(reads['WRITE_SIZE']['k_stream_copy'])):.1f} KiB per dispatch for {copy_kib:.0f} KiB",
+            f"# each, so FETCH_SIZE is scaled by {scale['FETCH_SIZE']:.4f} and WRITE_SIZE by {scale['WRITE_SIZE']:.4f}.",
+            f"# Both count L2 misses: a miss served by the 256 MiB Infinity Cache counts as well.",
+            f"#   traffic {traffic:.0f} B  algorithmic {alg} B  ratio {traffic / alg:.3f}",
+            f"kernel: {label}",
+            f"lattice: {'x'.join(map(str, dims))}",
+            f"fetch_kib_per_launch: {f:.1f}",
+            f"write_kib_per_launch: {w:.1f}",
+            f"fetch_scale: {scale['FETCH_SIZE']:.4f}",
+            f"write_scale: {scale['WRITE_SIZE']:.4f}",
+            f"traffic_bytes_per_launch: {traffic:.0f}",
+            f"algorithmic_bytes_per_launch: {alg}",
+            f"source_sha: {kernel_source_sha()}",
+        ]
+        path = os.path.join(PROFILES, f"traffic_{label}_{'x'.join(map(str, dims))}.txt")
+        with open(path, "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+        print(f"{label}: traffic / algorithmic = {traffic / alg:.3f} -> {os.path.relpath(path, ROOT)}")
+
+
 def main():
     args = parse()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace)
+        return
+    if args.summarize_traffic:
+        summarize_traffic(*args.summarize_traffic)
+        return
     dims = tuple(int(v) for v in args.dims.split(","))
     if args.cpu_sample_only:
         cpu_sample(dims)
