@@ -905,8 +905,10 @@ def main():
         "dslash": dsl,
         "roofline": {"bound": "hbm", "kernel": kern["kernel"], "achieved": kern["GB_per_s"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kern["frac_hbm"],
-                     "stream_ceiling_GB_per_s": ceiling["copy_GB_per_s"],
-                     "frac_of_stream_ceiling": kern["GB_per_s"] / ceiling["copy_GB_per_s"],
+                     "stream_copy_GB_per_s": ceiling["copy_GB_per_s"],
+                     "stream_read_GB_per_s": ceiling["read_GB_per_s"],
+                     "frac_of_stream_copy": kern["GB_per_s"] / ceiling["copy_GB_per_s"],
+                     "frac_of_stream_read": kern["GB_per_s"] / ceiling["read_GB_per_s"],
                      "traffic": traffic["bytes"] if traffic else None,
                      "algorithmic_bytes": kern["bytes_per_site"] * V,
                      "avg_launch_us": kern["avg_us"],
