@@ -139,6 +139,9 @@ def parse():
     ap.add_argument("--summarize-traffic", nargs=2, default=None, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic_*.txt from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) "
                          "of this benchmark, calibrated by its 8 GiB streaming copy")
+    ap.add_argument("--summarize-issue", default=None, metavar="DIR",
+                    help="write profiles/issue_hot_kernels_*.md from one rocprofv3 --pmc run of this benchmark "
+                         "with ISSUE_COUNTERS (instruction mix and VALU issue time per kernel)")
     return ap.parse_args()
 
 
@@ -651,8 +654,91 @@ def summarize_traffic(fetch_dir, write_dir, dims=DIMS):
         print(f"{label}: traffic / algorithmic = {traffic / alg:.3f} -> {os.path.relpath(path, ROOT)}")
 
 
+# one --pmc pass: 8 SQ counters and one GRBM counter (what a single pass can hold)
+ISSUE_COUNTERS = ("SQ_WAVES SQ_INSTS_VALU SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_INSTS_LDS SQ_INSTS_SALU "
+                  "SQ_WAIT_INST_ANY SQ_WAVE_CYCLES GRBM_GUI_ACTIVE")
+
+
+def summarize_issue(directory, dims=DIMS):
+    """Instruction mix and VALU issue time of the stored kernels.
+
+    SQ_INSTS_VALU counts wave-level VALU instructions over the chip; a wave64
+    VALU instruction occupies its SIMD for at least 4 cycles, so
+    SQ_INSTS_VALU x 4 / (SIMDs) is the fewest cycles the kernel's VALU work
+    can take. GRBM_GUI_ACTIVE counts the cycles the graphics engine was busy
+    during the dispatch, summed over the XCDs (it reads the XCD count times
+    the dispatch's length in cycles), so GRBM_GUI_ACTIVE / XCDs is the
+    dispatch's length in cycles at the clock it actually ran; their ratio is
+    the fraction of the kernel's cycles in which every SIMD would have to
+    issue a VALU instruction: near 1 the kernel is bound by VALU issue."""
+    import csv
+    import glob
+    rows = _rocprof_rows(directory, "counter_collection.csv")
+    agent = {}
+    for path in glob.glob(os.path.join(directory, "**", "*agent_info.csv"), recursive=True):
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r.get("Agent_Type") == "GPU":
+                    agent = r
+    simds = int(agent.get("Simd_Count", 1024))
+    xcds = int(agent.get("Num_Xcc", 8))
+    per, dur = {}, {}
+    for r in rows:
+        name = _short_name(r["Kernel_Name"])
+        per.setdefault(name, {}).setdefault(r["Counter_Name"], {})[r["Dispatch_Id"]] = float(r["Counter_Value"])
+        dur.setdefault(name, {})[r["Dispatch_Id"]] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    kernels = dict(TRAFFIC_KERNELS)
+    kernels["k_p_update_i8"] = ("k_p_update_ring<4>", loop_kernel_bytes("i8", True)["p_update"])
+    cmd = ("cd /tmp && TMPDIR=/tmp timeout -s KILL 300 rocprofv3 --pmc " + ISSUE_COUNTERS +
+           " -d $R/gpurun_out/pmc_issue -o p --output-format csv -- python3 $R/bench.py --steps 1 --warmup 1 "
+           "--inner i8 --fp64-steps 1 --dslash-reps 20 --no-cpu-baseline --no-other-rows")
+    lines = [
+        f"# Instruction mix and VALU issue time of the hot kernels on {'x'.join(map(str, dims))} (one MI355X)",
+        "# Commands (R = repository root on the GPU box):",
+        "#   " + cmd,
+        "#   python3 bench.py --summarize-issue $R/gpurun_out/pmc_issue",
+        f"# Agent: {simds} SIMDs, {xcds} XCDs. Per-wave figures are per wave64 (one site per lane).",
+        "# cycles = GRBM_GUI_ACTIVE / XCDs (the dispatch's length at the clock it ran; clock = cycles / time);",
+        "# VALU-issue = SQ_INSTS_VALU x 4 / SIMDs / cycles: the share of the dispatch's cycles that its VALU",
+        "# instructions alone occupy every SIMD (each wave64 VALU instruction holds its SIMD >= 4 cycles).",
+        "# wait = SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES: share of resident-wave time spent waiting for",
+        "# outstanding memory or LDS results. Means over the launches that did work.",
+        f"# source_sha: {kernel_source_sha()}",
+        "#",
+        "kernel | waves | VALU/wave | VMEM rd/wave | VMEM wr/wave | LDS/wave | SALU/wave | us (under counters) "
+        "| clock GHz | VALU-issue | wait",
+    ]
+    for label, (kname, _bps) in kernels.items():
+        if kname not in per:
+            continue
+        c = per[kname]
+        ids = [i for i in dur[kname] if "GRBM_GUI_ACTIVE" in c and i in c["GRBM_GUI_ACTIVE"]]
+        work = _working([dur[kname][i] for i in ids])
+        keep = {i for i in ids if dur[kname][i] in work}
+
+        def m(counter):
+            v = [c[counter][i] for i in keep if i in c.get(counter, {})]
+            return float(np.mean(v)) if v else float("nan")
+        waves = m("SQ_WAVES")
+        us = float(np.mean([dur[kname][i] for i in keep])) / 1e3
+        cycles = m("GRBM_GUI_ACTIVE") / xcds
+        issue = m("SQ_INSTS_VALU") * 4 / simds / cycles
+        lines.append(
+            f"{label} | {waves:.0f} | {m('SQ_INSTS_VALU') / waves:.0f} | {m('SQ_INSTS_VMEM_RD') / waves:.1f} | "
+            f"{m('SQ_INSTS_VMEM_WR') / waves:.1f} | {m('SQ_INSTS_LDS') / waves:.1f} | "
+            f"{m('SQ_INSTS_SALU') / waves:.0f} | {us:.1f} | {cycles / (us * 1e3):.2f} | {issue:.2f} | "
+            f"{m('SQ_WAIT_INST_ANY') / m('SQ_WAVE_CYCLES'):.2f}")
+    path = os.path.join(PROFILES, f"issue_hot_kernels_{'x'.join(map(str, dims))}.md")
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     args = parse()
+    if args.summarize_issue:
+        summarize_issue(args.summarize_issue)
+        return
     if args.summarize_trace:
         summarize_trace(args.summarize_trace)
         return
