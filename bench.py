@@ -326,8 +326,22 @@ def bench_batched(dev):
             "site_rhs_iterations_per_s": V * sum(its) / dt, "algorithmic_GB_per_s": alg / dt / 1e9,
             "frac_hbm": alg / dt / 1e9 / HBM_PEAK_GBS}
         del X
+    # the same 16 systems solved one after another by the single-system solver,
+    # for comparison (each call also packs the links again; a batched solve
+    # packs them once)
+    sequential = {}
+    for inner in ("f16", "i8"):
+        wd.cg_solve(U, B[0], 0.05, tol=TOL, inner=inner, workspace=ws)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        its = [wd.cg_solve(U, B[k], 0.05, tol=TOL, inner=inner, workspace=ws)[1]["iterations"] for k in range(16)]
+        torch.cuda.synchronize()
+        sequential[f"sequential_{inner}"] = {"schedule": "sixteen single solves", "inner": inner,
+                                             "seconds": time.perf_counter() - t, "iterations_max": max(its),
+                                             "iterations_mean": float(np.mean(its))}
     best = min(variants, key=lambda k: variants[k]["seconds"])
-    out = {"nrhs": 16, "lattice_xyzt": list(dims), **variants[best], "variants": variants}
+    out = {"nrhs": 16, "lattice_xyzt": list(dims), **variants[best], "variants": variants,
+           "single_solves": sequential}
     del U, B, ws
     return out
 
