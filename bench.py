@@ -81,16 +81,20 @@ CSRC = os.path.join(ROOT, "paper_2001_05218_amd", "csrc")
 PROFILES = os.path.join(ROOT, "profiles")
 
 
+# The translation unit of the stencil and CG-vector kernels whose counters are
+# stored (every kernel of TRAFFIC_KERNELS is built from these files alone).
+KERNEL_SOURCES = ("csrc/wd_kernels.hip", "csrc/wd_common.hpp", "csrc/wd_dslash.hpp", "csrc/wd_internal.hpp",
+                  "csrc/wd_reduce.hpp", "csrc/wd_tiled.hpp", "../include/wilson.h")
+
+
 def kernel_source_sha() -> str:
-    """SHA-256 over the device-code sources (.hip and headers; the host-only
-    .cpp is left out): a stored counter figure is only valid for the kernels
-    it was measured on."""
+    """SHA-256 over the sources the stored kernels are compiled from: a stored
+    counter figure is only valid for the kernels it was measured on."""
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".hpp")):
-            with open(os.path.join(CSRC, name), "rb") as f:
-                h.update(name.encode())
-                h.update(f.read())
+    for rel in KERNEL_SOURCES:
+        with open(os.path.normpath(os.path.join(CSRC, "..", rel)), "rb") as f:
+            h.update(os.path.basename(rel).encode())
+            h.update(f.read())
     return h.hexdigest()
 
 

@@ -218,6 +218,8 @@ struct SegList {
   int n;
 };
 
+constexpr size_t kMoveBlocks = 128;
+
 __global__ __launch_bounds__(kBlock) void k_ooc_move(SegList L) {
   const size_t total = L.start[L.n];
   const size_t stride = (size_t)gridDim.x * kBlock * 8;
@@ -347,7 +349,13 @@ struct Ooc {
   // device
   OocLayout L{};
   OocDevice* dev = nullptr;
-  std::vector<hipEvent_t> out_ev;       // per slab: its latest write-back has finished
+  // Per slab, the write-back of the previous sweep and of the current one
+  // (out_ev[par] and out_ev[par ^ 1]). No sweep reads host data that it
+  // writes itself (the search direction is double-buffered for that), so a
+  // slab's copy-in waits only for the previous sweep's write-backs of the
+  // slabs it reads: in stream order those finish after every earlier one.
+  std::vector<hipEvent_t> out_ev[2];
+  int par = 0;
   hipEvent_t in_ready[2]{}, comp_done[2]{}, set_free[2]{};
   int start = 0;                        // first slab of the current sweep order
   char* err = nullptr;
@@ -386,8 +394,12 @@ struct Ooc {
       return WD_ERR_HIP;
     }
     if (m.L.n == 0) return WD_OK;
+    // 128 workgroups (8 x 16 B in flight per thread, 4 MiB in all) keep the
+    // host link busy; more of them only crowd the slab kernels that run
+    // beside the copies (their host reads hold CU slots for microseconds).
+    // Measured on 16^3x32 under 64 MiB: 1024 -> 2.02 s, 128 -> 1.74 s, 32 -> 2.22 s.
     const size_t per = (size_t)kBlock * 8;
-    const size_t blocks = std::min<size_t>((m.words + per - 1) / per, 1024);
+    const size_t blocks = std::min<size_t>((m.words + per - 1) / per, kMoveBlocks);
     k_ooc_move<<<(unsigned)blocks, kBlock, 0, s>>>(m.L);
     OOC_TRY(hipGetLastError());
     return WD_OK;
@@ -459,11 +471,12 @@ struct Ooc {
       const int k = (start + i) % nslab;
       const int j = i & 1;
       OocSet& S = L.set[j];
+      const std::vector<hipEvent_t>& prev = out_ev[par];
       OOC_TRY(hipStreamWaitEvent(D.h2d, set_free[j], 0));
-      OOC_TRY(hipStreamWaitEvent(D.h2d, out_ev[k], 0));
+      OOC_TRY(hipStreamWaitEvent(D.h2d, prev[k], 0));
       if (window) {
-        OOC_TRY(hipStreamWaitEvent(D.h2d, out_ev[(k + nslab - 1) % nslab], 0));
-        OOC_TRY(hipStreamWaitEvent(D.h2d, out_ev[(k + 1) % nslab], 0));
+        OOC_TRY(hipStreamWaitEvent(D.h2d, prev[(k + nslab - 1) % nslab], 0));
+        OOC_TRY(hipStreamWaitEvent(D.h2d, prev[(k + 1) % nslab], 0));
       }
       Moves mi;
       in(k, S, mi);
@@ -478,9 +491,10 @@ struct Ooc {
       Moves mo;
       out(k, S, mo);
       if ((rc = launch_moves(mo, D.d2h))) return rc;
-      OOC_TRY(hipEventRecord(out_ev[k], D.d2h));
+      OOC_TRY(hipEventRecord(out_ev[par ^ 1][k], D.d2h));
       OOC_TRY(hipEventRecord(set_free[j], D.d2h));
     }
+    par ^= 1;
     return WD_OK;
   }
   void finalize(int fin) { launch_finalize_n(total_partials(), L.partials, L.st, fin, G_ALWAYS, dev->comp); }
@@ -691,8 +705,10 @@ int ooc_solve(const int Ldims[4], double mass, const void* U, const void* b, voi
     (void)hipStreamSynchronize(D.d2h);
     for (hipEvent_t e : evs) (void)hipEventDestroy(e);
   };
-  o.out_ev.assign(o.nslab, nullptr);
-  for (int k = 0; k < o.nslab && !rc; ++k) rc = make_ev(&o.out_ev[k]);
+  for (int h = 0; h < 2; ++h) {
+    o.out_ev[h].assign(o.nslab, nullptr);
+    for (int k = 0; k < o.nslab && !rc; ++k) rc = make_ev(&o.out_ev[h][k]);
+  }
   for (int j = 0; j < 2 && !rc; ++j)
     rc = make_ev(&o.in_ready[j]) || make_ev(&o.comp_done[j]) || make_ev(&o.set_free[j]) ? WD_ERR_HIP : WD_OK;
   hipEvent_t caller_ev = nullptr;
@@ -707,7 +723,8 @@ int ooc_solve(const int Ldims[4], double mass, const void* U, const void* b, voi
     OOC_TRY(hipStreamWaitEvent(D.h2d, caller_ev, 0));
     OOC_TRY(hipStreamWaitEvent(D.comp, caller_ev, 0));
     OOC_TRY(hipStreamWaitEvent(D.d2h, caller_ev, 0));
-    for (hipEvent_t e : o.out_ev) OOC_TRY(hipEventRecord(e, D.d2h));
+    for (int h = 0; h < 2; ++h)
+      for (hipEvent_t e : o.out_ev[h]) OOC_TRY(hipEventRecord(e, D.d2h));
     for (int j = 0; j < 2; ++j) OOC_TRY(hipEventRecord(o.set_free[j], D.d2h));
 
     launch_init_state(o.L.st, p->tol, 0, 0.0, o.L.hist, p->history_len, D.comp);
