@@ -732,92 +732,149 @@ __device__ __forceinline__ void outer_acc(const double u[12], const double v[12]
   }
 }
 
-// Sites s0 .. s0 + n - 1 of a canonical spinor field into registers, one site
-// per thread, through LDS: the block's records form one contiguous range, read
-// with consecutive 16-byte words across the lanes and then transposed. A
-// thread reading its own 192-byte record directly would touch a cache line per
-// word for 16 useful bytes, and the force kernel was bound by exactly those
-// cache-line lookups. Threads of sites beyond the lattice get zeros.
-__device__ __forceinline__ void load_own(const double2* __restrict__ src, int s0, int n,
-                                         double2 (*stage)[kBlock + 1], double v[24]) {
-  const double2* base = src + (size_t)s0 * 12;
-  for (int q = threadIdx.x; q < n * 12; q += kBlock) {
-    const int site = q / 12;
-    stage[q - site * 12][site] = base[q];
-  }
-  __syncthreads();
+// ---- force kernel: one direction per wavefront. A workgroup owns 64
+// consecutive sites (linear order) and stages their records of a and b in LDS
+// once, coalesced; wavefront mu then computes G_mu for the 64 sites. Each
+// wavefront has a single dependent load (its neighbours) between the staging
+// and the store, where a workgroup that walks the four directions in turn has
+// four, and the a and b records are read from memory once per workgroup.
+constexpr int kForceSites = 64;
+constexpr int kForcePad = kForceSites + 1;   // LDS row stride (bank spread)
+
+__device__ __forceinline__ void staged_record(const double2* lds, int field, int site, double v[24]) {
 #pragma unroll
   for (int w = 0; w < 12; ++w) {
-    const double2 d = (int)threadIdx.x < n ? stage[w][threadIdx.x] : make_double2(0.0, 0.0);
+    const double2 d = lds[(field * 12 + w) * kForcePad + site];
     v[2 * w] = d.x;
     v[2 * w + 1] = d.y;
   }
-  __syncthreads();   // the stage is rewritten next
 }
 
-// G_mu at a site whose own spinors a(x), b(x) are in registers; the
-// neighbours a(x + mu), b(x + mu) are read from memory. 18 reals.
+__device__ __forceinline__ int fwd_site(const Geom& g, int s, int mu) {
+  int c[4];
+  site_coords(g, s, c);
+  const int st = g.stride[mu];
+  return (c[mu] == g.L[mu] - 1) ? s - st * (g.L[mu] - 1) : s + st;
+}
+
+// 24 reals of a record from a generic pointer, word stride st (16-byte words)
+__device__ __forceinline__ void load_record(const double2* p, int st, double v[24]) {
+#pragma unroll
+  for (int w = 0; w < 12; ++w) {
+    const double2 d = p[w * st];
+    v[2 * w] = d.x;
+    v[2 * w + 1] = d.y;
+  }
+}
+
+// The 64 records src[idx(lane)] of a wavefront into its LDS region buf
+// ([word][lane], stride kForcePad), loaded 12 lanes to a record so that each
+// load instruction covers about six whole records instead of one word of 64,
+// then returned to each lane from LDS.
+__device__ __forceinline__ void gather_wave(const double2* __restrict__ src, int idx, int l, double2* buf,
+                                            double v[24]) {
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    const int e = k * 64 + l;            // element e of the 64 x 12 words
+    const int r = e / 12;
+    const int w = e - r * 12;
+    const int sr = __shfl(idx, r, 64);
+    buf[w * kForcePad + r] = src[(size_t)sr * 12 + w];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+  for (int w = 0; w < 12; ++w) {
+    const double2 d = buf[w * kForcePad + l];
+    v[2 * w] = d.x;
+    v[2 * w + 1] = d.y;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// G_mu at the 64 sites of the block. x and y: the neighbour's record from the
+// staged block when it lies there (one generic load path, LDS or memory); z
+// and t: neighbours lie outside the block, gathered cooperatively.
 template <int MU>
-__device__ __forceinline__ void force_site(const double aown[24], const double bown[24], const CanonSpinor& a,
-                                           const CanonSpinor& b, int sf, double f[18]) {
-  double psi[24], h[12], k[12];
-  project<MU, -1>(aown, h);   // (1 - g) a(x), upper half
-  b.load(sf, psi);
-  project<MU, -1>(psi, k);    // matching combination of b(x + mu)
+__device__ __forceinline__ void force_wave(const Geom& g, const double2* lds, double2* wbuf, const CanonSpinor& a,
+                                           const CanonSpinor& b, int s0, int n, int l, double f[18]) {
+  const int sf = fwd_site(g, s0 + min(l, n - 1), MU);
+  const int j = sf - s0;
+  const bool in_block = j >= 0 && j < n;
+  const double2* nb_a = in_block ? lds + j : a.data + (size_t)sf * 12;
+  const double2* nb_b = in_block ? lds + 12 * kForcePad + j : b.data + (size_t)sf * 12;
+  const int st = in_block ? kForcePad : 1;
+  double v[24], h[12], k[12];
+  staged_record(lds, 0, l, v);
+  project<MU, -1>(v, h);              // (1 - g) a(x), upper half
+  if constexpr (MU >= 2) gather_wave(b.data, sf, l, wbuf, v);
+  else load_record(nb_b, st, v);
+  project<MU, -1>(v, k);              // matching combination of b(x + mu)
   outer_acc(h, k, f);
-  project<MU, +1>(bown, h);   // (1 + g) b(x)
-  a.load(sf, psi);
-  project<MU, +1>(psi, k);    // (1 + g) a(x + mu)
+  // finish this half before the next record's loads are issued (the
+  // compiler would otherwise hold all four records in registers at once)
+#pragma unroll
+  for (int i = 0; i < 18; ++i) asm volatile("" : "+v"(f[i]) : : "memory");
+  staged_record(lds, 1, l, v);
+  project<MU, +1>(v, h);              // (1 + g) b(x)
+  if constexpr (MU >= 2) gather_wave(a.data, sf, l, wbuf, v);
+  else load_record(nb_a, st, v);
+  project<MU, +1>(v, k);              // (1 + g) a(x + mu)
   outer_acc(h, k, f);
 }
 
-// One workgroup: 256 consecutive sites (linear order). For each direction the
-// block's 256 x 9 link entries are staged in LDS and stored as one contiguous,
-// coalesced range of F (a thread's own 144-byte record would otherwise be
-// written as nine 16-byte pieces 144 bytes apart from its neighbours').
-template <int MU>
-__device__ __forceinline__ void force_dir(Geom g, const double aown[24], const double bown[24], const CanonSpinor& a,
-                                          const CanonSpinor& b, double c, int accumulate, double2* __restrict__ F,
-                                          int s0, const Nbrs& nb, double2 (*stage)[kBlock + 1]) {
-  const int s = s0 + threadIdx.x;
+__global__ __launch_bounds__(kBlock) void k_force(Geom g, CanonSpinor a, CanonSpinor b, double coeff,
+                                                  int accumulate, double2* __restrict__ F) {
+  // rows of kForcePad words: [0, 24) the block's records of a and b
+  // ([field][word][site]), [24, 48) the z and t wavefronts' gathers; after the
+  // second barrier [0, 36) the link entries ([mu][entry][site])
+  __shared__ double2 lds[48 * kForcePad];
+  const int s0 = blockIdx.x * kForceSites;
+  const int n = min(kForceSites, g.V - s0);
+  const int nw = n * 12;
+  for (int q = threadIdx.x; q < 2 * nw; q += kBlock) {
+    const int fld = q >= nw;
+    const int r = q - fld * nw;
+    const int site = r / 12;
+    lds[(fld * 12 + (r - site * 12)) * kForcePad + site] = (fld ? b.data : a.data)[(size_t)s0 * 12 + r];
+  }
+  __syncthreads();
+  const int mu = threadIdx.x >> 6;
+  const int l = threadIdx.x & 63;
   double f[18];
 #pragma unroll
   for (int i = 0; i < 18; ++i) f[i] = 0.0;
-  if (s < g.V) force_site<MU>(aown, bown, a, b, nb.fwd[MU], f);
+  // every lane runs (the gathers need the whole wavefront); lanes past the
+  // block's n sites compute a copy of the last site and store nothing
+  if (mu == 0) force_wave<0>(g, lds, nullptr, a, b, s0, n, l, f);
+  else if (mu == 1) force_wave<1>(g, lds, nullptr, a, b, s0, n, l, f);
+  else if (mu == 2) force_wave<2>(g, lds, lds + 24 * kForcePad, a, b, s0, n, l, f);
+  else force_wave<3>(g, lds, lds + 36 * kForcePad, a, b, s0, n, l, f);
+  __syncthreads();   // every record read: the buffer now takes the link entries
+  const double c = 0.5 * coeff;
 #pragma unroll
-  for (int e = 0; e < 9; ++e) stage[e][threadIdx.x] = make_double2(c * f[2 * e], c * f[2 * e + 1]);
+  for (int e = 0; e < 9; ++e) lds[(mu * 9 + e) * kForcePad + l] = make_double2(c * f[2 * e], c * f[2 * e + 1]);
   __syncthreads();
-  const int n = min(kBlock, g.V - s0) * 9;
-  double2* dst = F + ((size_t)MU * g.V + s0) * 9;
-  for (int q = threadIdx.x; q < n; q += kBlock) {
-    double2 v = stage[q % 9][q / 9];
+  const int per = n * 9;
+  for (int q = threadIdx.x; q < 4 * per; q += kBlock) {
+    const int m = q / per;
+    const int r = q - m * per;
+    const int site = r / 9;
+    double2 v = lds[(m * 9 + (r - site * 9)) * kForcePad + site];
+    double2* dst = F + ((size_t)m * g.V + s0) * 9 + r;
+    // G is written once and read by no later workgroup: streamed past the
+    // caches, which keep the records that neighbouring blocks gather
+    typedef double v2d __attribute__((ext_vector_type(2)));
     if (accumulate) {
-      const double2 o = dst[q];
+      const v2d o = __builtin_nontemporal_load(reinterpret_cast<const v2d*>(dst));
       v.x += o.x;
       v.y += o.y;
     }
-    dst[q] = v;
+    st_nt(dst, v);
   }
-  __syncthreads();   // the stage is rewritten for the next direction
-}
-
-__global__ __launch_bounds__(kBlock) void k_force(Geom g, CanonSpinor a, CanonSpinor b, double coeff, int accumulate,
-                                                  double2* __restrict__ F) {
-  // rows padded by one word: the transposing writes of consecutive words of a
-  // record then fall in different banks
-  __shared__ double2 stage[12][kBlock + 1];
-  const int s0 = blockIdx.x * kBlock;
-  const int n = min(kBlock, g.V - s0);
-  const int s = s0 + threadIdx.x;
-  const Nbrs nb = neighbours(g, s < g.V ? s : s0);
-  const double c = 0.5 * coeff;
-  double aown[24], bown[24];
-  load_own(a.data, s0, n, stage, aown);
-  load_own(b.data, s0, n, stage, bown);
-  force_dir<0>(g, aown, bown, a, b, c, accumulate, F, s0, nb, stage);
-  force_dir<1>(g, aown, bown, a, b, c, accumulate, F, s0, nb, stage);
-  force_dir<2>(g, aown, bown, a, b, c, accumulate, F, s0, nb, stage);
-  force_dir<3>(g, aown, bown, a, b, c, accumulate, F, s0, nb, stage);
 }
 
 __global__ void k_init_state(SolverState* st, double tol, int interval, double delta, double* hist,
@@ -1150,7 +1207,8 @@ void launch_norm2(const Geom& g, SpinorBuf v, int gate, int fin, SolverState* st
 void launch_force(const Geom& g, const void* a, const void* b, double coeff, int accumulate, void* F, hipStream_t s) {
   CanonSpinor ca{const_cast<double2*>(static_cast<const double2*>(a))};
   CanonSpinor cb{const_cast<double2*>(static_cast<const double2*>(b))};
-  k_force<<<grid_of(g), kBlock, 0, s>>>(g, ca, cb, coeff, accumulate, static_cast<double2*>(F));
+  k_force<<<(unsigned)((g.V + kForceSites - 1) / kForceSites), kBlock, 0, s>>>(g, ca, cb, coeff, accumulate,
+                                                                               static_cast<double2*>(F));
 }
 
 }  // namespace wd
