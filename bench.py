@@ -369,7 +369,11 @@ def bench_force(dev, a, b, reps=20):
     avg = e0.elapsed_time(e1) / 1e3 / reps
     gbs = FORCE_BYTES * V / avg / 1e9
     del F
-    return {"avg_us": avg * 1e6, "bytes_per_site": FORCE_BYTES, "GB_per_s": gbs, "frac_hbm": gbs / HBM_PEAK_GBS}
+    out = {"avg_us": avg * 1e6, "bytes_per_site": FORCE_BYTES, "GB_per_s": gbs, "frac_hbm": gbs / HBM_PEAK_GBS}
+    stored = stored_traffic("k_force", dims)
+    out["traffic"] = stored["bytes"] if stored else None
+    out["traffic_source"] = stored["file"] if stored else None
+    return out
 
 
 def bench_autograd(dev):
@@ -481,8 +485,10 @@ def ooc_pcie_bytes(dims, ts, nslab, iters):
     """Bytes one out-of-core solve moves each way: per slab k of t_k planes, an
     iteration copies in the links of t_k + 1 planes twice (t = D p; D^+ t), the
     r, p and t windows (t_k + 2 planes each), x and r (t_k planes each); it
-    copies out p, t, x and r (t_k planes each). Set-up (D^+ b; b' = r = p; x = 0),
-    the last deferred x update and the final residual (D x; b' - D^+ t) are
+    copies out p, t, x and r (t_k planes each). The solver keeps one iteration
+    queued beyond the one whose state it reads, so a converged solve runs
+    iters + 1 iterations' copies, the last of which also completes x. Set-up
+    (D^+ b; b' = r = p; x = 0) and the final residual (D x; b' - D^+ t) are
     added once."""
     lx, ly, lz, lt = dims
     plane = lx * ly * lz
@@ -490,12 +496,11 @@ def ooc_pcie_bytes(dims, ts, nslab, iters):
     h2d = d2h = 0
     for k in range(nslab):
         t = min(ts, lt - k * ts)
-        h2d += iters * (2 * (t + 1) * lk + (3 * (t + 2) + 2 * t) * sp)
-        d2h += iters * 4 * t * sp
+        h2d += (iters + 1) * (2 * (t + 1) * lk + (3 * (t + 2) + 2 * t) * sp)
+        d2h += (iters + 1) * 4 * t * sp
         h2d += (t + 1) * lk + (t + 2) * sp          # set-up
-        h2d += 2 * t * sp                           # last x update
         h2d += 2 * ((t + 1) * lk + (t + 2) * sp) + t * sp   # D x; b' - D^+ t
-        d2h += 4 * t * sp + t * sp + t * sp + 2 * t * sp
+        d2h += 4 * t * sp + t * sp + 2 * t * sp
     return h2d, d2h
 
 
@@ -594,16 +599,30 @@ def _working(durations):
 
 
 def summarize_trace(directory):
+    """Markdown kernel-time table of a rocprofv3 kernel trace; then, for the
+    kernels launched with more than one grid size (single-system and
+    16-system lockstep launches, several lattices), the same per grid size."""
     rows = _rocprof_rows(directory, "kernel_trace.csv")
-    per = {}
+    per, by_grid = {}, {}
     for r in rows:
-        per.setdefault(_short_name(r["Kernel_Name"]), []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+        name = _short_name(r["Kernel_Name"])
+        d = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        per.setdefault(name, []).append(d)
+        by_grid.setdefault(name, {}).setdefault(int(r["Grid_Size_X"]), []).append(d)
     total = sum(sum(v) for v in per.values())
     print("name | calls | working calls | average us (working) | total ms | % of GPU time")
     for name, d in sorted(per.items(), key=lambda kv: -sum(kv[1])):
         w = _working(d)
         print(f"{name} | {len(d)} | {len(w)} | {sum(w) / len(w) / 1e3:.1f} | {sum(d) / 1e6:.1f} | "
               f"{100.0 * sum(d) / total:.1f}")
+    multi = {n: g for n, g in by_grid.items() if len(g) > 1}
+    if multi:
+        print("#")
+        print("# per grid size (threads) | calls | working calls | average us (working)")
+        for name in sorted(multi):
+            for gs, d in sorted(multi[name].items()):
+                w = _working(d)
+                print(f"{name} | grid {gs} | {len(d)} | {len(w)} | {sum(w) / len(w) / 1e3:.1f}")
 
 
 # kernels whose HBM traffic is stored: label -> (kernel name, algorithmic bytes per site)
@@ -614,6 +633,7 @@ TRAFFIC_KERNELS = {
     "k_wilson_tiled_f16_rows2": ("k_wilson_tiled<3, true, false>", loop_kernel_bytes("f16", True)["D"]),
     "k_wilson_packed_f64": ("k_wilson_packed<0, false, true>", loop_kernel_bytes("f64")["D"]),
     "k_cg_update_f64": ("k_cg_update<0, 0, true, true>", loop_kernel_bytes("f64")["update"]),
+    "k_force": ("k_force", FORCE_BYTES),
 }
 
 
@@ -635,7 +655,7 @@ def summarize_traffic(fetch_dir, write_dir, dims=DIMS):
     scale = {c: copy_kib / float(np.mean(reads[c]["k_stream_copy"])) for c in reads}
     src = "cd /tmp && TMPDIR=/tmp timeout -s KILL 300 rocprofv3 --pmc {c} -d $R/gpurun_out/pmc_{c} -o p " \
           "--output-format csv -- python3 $R/bench.py --steps 1 --warmup 1 --inner i8 --fp64-steps 1 " \
-          "--dslash-reps 20 --no-cpu-baseline --no-other-rows"
+          "--dslash-reps 20 --no-cpu-baseline --other-rows force"
     for label, (kname, bps) in TRAFFIC_KERNELS.items():
         if kname not in reads["FETCH_SIZE"] or kname not in reads["WRITE_SIZE"]:
             continue
@@ -709,7 +729,7 @@ def summarize_issue(directory, dims=DIMS):
     kernels["k_p_update_i8"] = ("k_p_update_ring<4>", loop_kernel_bytes("i8", True)["p_update"])
     cmd = ("cd /tmp && TMPDIR=/tmp timeout -s KILL 300 rocprofv3 --pmc " + ISSUE_COUNTERS +
            " -d $R/gpurun_out/pmc_issue -o p --output-format csv -- python3 $R/bench.py --steps 1 --warmup 1 "
-           "--inner i8 --fp64-steps 1 --dslash-reps 20 --no-cpu-baseline --no-other-rows")
+           "--inner i8 --fp64-steps 1 --dslash-reps 20 --no-cpu-baseline --other-rows force")
     lines = [
         f"# Instruction mix and VALU issue time of the hot kernels on {'x'.join(map(str, dims))} (one MI355X)",
         "# Commands (R = repository root on the GPU box):",

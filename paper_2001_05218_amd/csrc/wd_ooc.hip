@@ -295,8 +295,8 @@ OocLayout ooc_layout(void* base, int plane, int T, int ts, int hist_len) {
 // priority, non-blocking).
 struct OocDevice {
   hipStream_t h2d = nullptr, comp = nullptr, d2h = nullptr;
-  SolverState* mirror = nullptr;   // pinned
-  hipEvent_t mirror_ev = nullptr;
+  SolverState* mirror = nullptr;   // pinned, two slots (one iteration runs ahead)
+  hipEvent_t mirror_ev[2] = {nullptr, nullptr};
   bool ready = false;
 };
 std::mutex g_ooc_mu;
@@ -324,8 +324,9 @@ int ooc_device(OocDevice** out, char* err, size_t errlen) {
     OOC_TRY(hipStreamCreateWithFlags(&d.h2d, hipStreamNonBlocking));
     OOC_TRY(hipStreamCreateWithFlags(&d.comp, hipStreamNonBlocking));
     OOC_TRY(hipStreamCreateWithFlags(&d.d2h, hipStreamNonBlocking));
-    OOC_TRY(hipHostMalloc(reinterpret_cast<void**>(&d.mirror), sizeof(SolverState), hipHostMallocDefault));
-    OOC_TRY(hipEventCreateWithFlags(&d.mirror_ev, hipEventDisableTiming));
+    OOC_TRY(hipHostMalloc(reinterpret_cast<void**>(&d.mirror), 2 * sizeof(SolverState), hipHostMallocDefault));
+    OOC_TRY(hipEventCreateWithFlags(&d.mirror_ev[0], hipEventDisableTiming));
+    OOC_TRY(hipEventCreateWithFlags(&d.mirror_ev[1], hipEventDisableTiming));
     d.ready = true;
   }
   *out = &d;
@@ -497,7 +498,9 @@ struct Ooc {
     par ^= 1;
     return WD_OK;
   }
-  void finalize(int fin) { launch_finalize_n(total_partials(), L.partials, L.st, fin, G_ALWAYS, dev->comp); }
+  void finalize(int fin, int gate = G_ALWAYS) {
+    launch_finalize_n(total_partials(), L.partials, L.st, fin, gate, dev->comp);
+  }
 
   // ---- the sweeps of the solver
   // b' = D^+ b (source) or b (normal); r = p = b'; ||b'||^2 -> bnorm, rho; x = 0 if asked
@@ -569,7 +572,7 @@ struct Ooc {
     int rc = sweep(true, in, kern, out);
     if (rc) return rc;
     std::swap(p, p_next);
-    finalize(F_ALPHA);
+    finalize(F_ALPHA, G_ITER);   // frozen once the solve has stopped (see the loop)
     return WD_OK;
   }
   // S2: r -= alpha D^+ t; ||r||^2 -> beta
@@ -586,7 +589,7 @@ struct Ooc {
     auto out = [&](int k, OocSet& S, Moves& m) { slab_out(m, r, S.s[0], k); };
     int rc = sweep(true, in, kern, out);
     if (rc) return rc;
-    finalize(F_BETA);
+    finalize(F_BETA, G_ITER);
     return WD_OK;
   }
   // the deferred x += alpha p of the last iteration
@@ -622,15 +625,16 @@ struct Ooc {
     finalize(fin);
     return WD_OK;
   }
-  // the device state, after everything queued so far on the kernel stream
-  int post_state() {
-    OOC_TRY(hipMemcpyAsync(dev->mirror, L.st, sizeof(SolverState), hipMemcpyDeviceToHost, dev->comp));
-    OOC_TRY(hipEventRecord(dev->mirror_ev, dev->comp));
+  // the device state, after everything queued so far on the kernel stream,
+  // into mirror slot k
+  int post_state(int k) {
+    OOC_TRY(hipMemcpyAsync(dev->mirror + k, L.st, sizeof(SolverState), hipMemcpyDeviceToHost, dev->comp));
+    OOC_TRY(hipEventRecord(dev->mirror_ev[k], dev->comp));
     return WD_OK;
   }
-  int wait_state(SolverState* out) {
-    OOC_TRY(hipEventSynchronize(dev->mirror_ev));
-    *out = *dev->mirror;
+  int wait_state(int k, SolverState* out) {
+    OOC_TRY(hipEventSynchronize(dev->mirror_ev[k]));
+    *out = dev->mirror[k];
     return WD_OK;
   }
 };
@@ -735,34 +739,59 @@ int ooc_solve(const int Ldims[4], double mass, const void* U, const void* b, voi
       // r = b' - D^+ D x0, p = r
       if ((r2 = o.sweep_D(o.x, F_NONE)) || (r2 = o.sweep_residual(F_RHO_INIT, true))) return r2;
     }
+    // The host reads the state of one iteration while the next is already
+    // queued, so that the copies of consecutive iterations overlap. The
+    // alpha and beta updates are gated on the state: an iteration queued past
+    // the one that stopped the solve changes no scalar, and its first sweep
+    // applies the stopping iteration's deferred x += alpha p (its second
+    // sweep leaves a residual that the confirmation below recomputes).
+    int slot = 0, wait_slot = 0, queued = 0;
+    auto sync_state = [&](SolverState* out) -> int {   // everything queued so far
+      int rc = o.post_state(slot);
+      if (!rc) rc = o.wait_state(slot, out);
+      return rc;
+    };
     SolverState st{};
-    if ((r2 = o.post_state()) || (r2 = o.wait_state(&st))) return r2;
+    if ((r2 = sync_state(&st))) return r2;
     int restarts = 0;
     // alpha = beta = 0 (from the state's initialisation): the first S1 sets
     // p = r and adds nothing to x
     bool pending_x = false;   // x lacks the last alpha p
-    while (st.status == 0 && st.iter < p->max_iter) {
-      if ((r2 = o.sweep_s1()) || (r2 = o.sweep_s2())) return r2;
-      pending_x = true;
-      if ((r2 = o.post_state()) || (r2 = o.wait_state(&st))) return r2;
-      if (st.status == 1) {
-        // complete x, then confirm with the residual recomputed from it
-        if ((r2 = o.sweep_x_update())) return r2;
-        pending_x = false;
-        if ((r2 = o.sweep_D(o.x, F_NONE)) || (r2 = o.sweep_residual(F_TRUE, true))) return r2;
-        if ((r2 = o.post_state()) || (r2 = o.wait_state(&st))) return r2;
-        if (st.rho_true <= st.stop2 || st.iter >= p->max_iter || restarts >= 5) break;
-        ++restarts;   // the recurrence drifted: continue from the recomputed residual (r = p = it)
-        launch_restart(o.L.st, D.comp);
-        k_ooc_reset_ab<<<1, 64, 0, D.comp>>>(o.L.st);
-        if ((r2 = o.post_state()) || (r2 = o.wait_state(&st))) return r2;
+    for (;;) {
+      while (st.status == 0 && queued < 2 && st.iter + queued < p->max_iter) {
+        if ((r2 = o.sweep_s1()) || (r2 = o.sweep_s2()) || (r2 = o.post_state(slot))) return r2;
+        slot ^= 1;
+        ++queued;
       }
+      if (queued == 0) break;   // max_iter reached
+      if ((r2 = o.wait_state(wait_slot, &st))) return r2;
+      wait_slot ^= 1;
+      --queued;
+      pending_x = true;
+      if (st.status == 0) continue;
+      while (queued > 0) {      // the iteration queued beyond the stop: x is complete after it
+        if ((r2 = o.wait_state(wait_slot, &st))) return r2;
+        wait_slot ^= 1;
+        --queued;
+        pending_x = false;
+      }
+      if (st.status != 1) break;   // breakdown or NaN
+      // complete x, then confirm with the residual recomputed from it
+      if (pending_x && (r2 = o.sweep_x_update())) return r2;
+      pending_x = false;
+      if ((r2 = o.sweep_D(o.x, F_NONE)) || (r2 = o.sweep_residual(F_TRUE, true))) return r2;
+      if ((r2 = sync_state(&st))) return r2;
+      if (st.rho_true <= st.stop2 || st.iter >= p->max_iter || restarts >= 5) break;
+      ++restarts;   // the recurrence drifted: continue from the recomputed residual (r = p = it)
+      launch_restart(o.L.st, D.comp);
+      k_ooc_reset_ab<<<1, 64, 0, D.comp>>>(o.L.st);
+      if ((r2 = sync_state(&st))) return r2;
     }
     if (pending_x && st.status >= 0 && (r2 = o.sweep_x_update())) return r2;
     if (st.status == 0 || (st.status == 1 && st.rho_true > st.stop2)) {
       // stopped by max_iter: the true residual of the last iterate
       if ((r2 = o.sweep_D(o.x, F_NONE)) || (r2 = o.sweep_residual(F_TRUE, false))) return r2;
-      if ((r2 = o.post_state()) || (r2 = o.wait_state(&st))) return r2;
+      if ((r2 = sync_state(&st))) return r2;
     }
     if (p->history && p->history_len > 0) {
       const int n = std::min(st.iter, p->history_len);
