@@ -140,9 +140,9 @@ def parse():
     ap.add_argument("--cpu-plan-part", default=None, help=argparse.SUPPRESS)
     ap.add_argument("--summarize-trace", default=None, metavar="DIR",
                     help="print a markdown kernel-time table from a rocprofv3 --kernel-trace output directory")
-    ap.add_argument("--summarize-traffic", nargs=2, default=None, metavar=("FETCH_DIR", "WRITE_DIR"),
-                    help="write profiles/traffic_*.txt from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) "
-                         "of this benchmark, calibrated by its 8 GiB streaming copy")
+    ap.add_argument("--summarize-traffic", nargs="+", default=None, metavar="DIR",
+                    help="write profiles/traffic_*.txt from rocprofv3 --pmc runs of this benchmark: FETCH_SIZE, "
+                         "WRITE_SIZE and (optional third directory) RDREQ_COUNTERS, the read requests by size")
     ap.add_argument("--summarize-issue", default=None, metavar="DIR",
                     help="write profiles/issue_hot_kernels_*.md from one rocprofv3 --pmc run of this benchmark "
                          "with ISSUE_COUNTERS (instruction mix and VALU issue time per kernel)")
@@ -637,58 +637,88 @@ TRAFFIC_KERNELS = {
 }
 
 
-def summarize_traffic(fetch_dir, write_dir, dims=DIMS):
-    """Per-launch FETCH_SIZE and WRITE_SIZE (KiB) of the stored kernels, each
-    scaled by what the counter reads for the benchmark's 8 GiB streaming copy
-    (k_stream_copy: bytes read = bytes written = 8 GiB, far beyond the 256 MiB
-    Infinity Cache), means over the launches that did work."""
+# one --pmc pass of L2-to-memory read requests by size (4 TCC counters)
+RDREQ_COUNTERS = "TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum"
+
+
+def summarize_traffic(fetch_dir, write_dir, rdreq_dir=None, dims=DIMS):
+    """Per-launch memory traffic of the stored kernels (means over the
+    launches that did work).
+
+    Reads: with a request-size pass (rdreq_dir), exactly 32 n32 + 64 n64 +
+    128 n128 bytes from the L2's read requests to memory by size. FETCH_SIZE
+    is kept as a cross-check: its formula counts the 128-byte requests only
+    through TCC_BUBBLE, which reads zero here, so it counts a 128-byte request
+    as 64 bytes; scaled by what it reads for the benchmark's 8 GiB streaming
+    copy (factor 2, exact for a kernel whose reads are all 128-byte requests)
+    it overstates kernels that also make 32- and 64-byte requests. Writes:
+    WRITE_SIZE (32- and 64-byte requests, exact), with the same copy as check."""
     V = int(np.prod(dims))
     reads = {}
-    for directory, counter in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
-        per = {}
+    passes = [(fetch_dir, ("FETCH_SIZE",)), (write_dir, ("WRITE_SIZE",))]
+    if rdreq_dir:
+        passes.append((rdreq_dir, tuple(RDREQ_COUNTERS.split())))
+    for directory, counters in passes:
         for r in _rocprof_rows(directory, "counter_collection.csv"):
-            if r["Counter_Name"] != counter:
-                continue
-            per.setdefault(_short_name(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
-        reads[counter] = per
+            if r["Counter_Name"] in counters:
+                reads.setdefault(r["Counter_Name"], {}).setdefault(_short_name(r["Kernel_Name"]), []).append(
+                    float(r["Counter_Value"]))
     copy_kib = (8 << 30) / 1024
-    scale = {c: copy_kib / float(np.mean(reads[c]["k_stream_copy"])) for c in reads}
-    src = "cd /tmp && TMPDIR=/tmp timeout -s KILL 300 rocprofv3 --pmc {c} -d $R/gpurun_out/pmc_{c} -o p " \
+
+    def mean(counter, kname):
+        return float(np.mean(_working(reads[counter][kname])))
+
+    def exact_reads(kname):   # bytes, and the requests not accounted for by the three sizes
+        n32, n64, n128 = (mean(f"TCC_EA0_RDREQ_{b}B_sum", kname) for b in (32, 64, 128))
+        return 32 * n32 + 64 * n64 + 128 * n128, mean("TCC_EA0_RDREQ_sum", kname) - (n32 + n64 + n128)
+
+    scale = {c: copy_kib / mean(c, "k_stream_copy") for c in ("FETCH_SIZE", "WRITE_SIZE")}
+    cmd = "cd /tmp && TMPDIR=/tmp timeout -s KILL 300 rocprofv3 --pmc {c} -d $R/gpurun_out/pmc_{d} -o p " \
           "--output-format csv -- python3 $R/bench.py --steps 1 --warmup 1 --inner i8 --fp64-steps 1 " \
           "--dslash-reps 20 --no-cpu-baseline --other-rows force"
+    cmds = [cmd.format(c="FETCH_SIZE", d="FETCH_SIZE"), cmd.format(c="WRITE_SIZE", d="WRITE_SIZE")]
+    summ = "python3 bench.py --summarize-traffic $R/gpurun_out/pmc_FETCH_SIZE $R/gpurun_out/pmc_WRITE_SIZE"
+    if rdreq_dir:
+        cmds.append(cmd.format(c=RDREQ_COUNTERS, d="RDREQ"))
+        summ += " $R/gpurun_out/pmc_RDREQ"
+        copy_rd, copy_rest = exact_reads("k_stream_copy")
     for label, (kname, bps) in TRAFFIC_KERNELS.items():
         if kname not in reads["FETCH_SIZE"] or kname not in reads["WRITE_SIZE"]:
             continue
-        f = float(np.mean(_working(reads["FETCH_SIZE"][kname])))
-        w = float(np.mean(_working(reads["WRITE_SIZE"][kname])))
-        traffic = (f * scale["FETCH_SIZE"] + w * scale["WRITE_SIZE"]) * 1024
+        f = mean("FETCH_SIZE", kname)
+        w = mean("WRITE_SIZE", kname)
+        fetch_scaled = f * scale["FETCH_SIZE"] * 1024
+        write_b = w * scale["WRITE_SIZE"] * 1024
+        lines = [f"# Memory traffic of {label} on {'x'.join(map(str, dims))} (one launch = {V} sites)",
+                 f"# kernel: {kname}", "# Commands (R = repository root on the GPU box):"]
+        lines += ["#   " + c for c in cmds] + ["#   " + summ]
+        lines.append(f"# The 8 GiB streaming copy k_stream_copy (reads = writes = {copy_kib:.0f} KiB) reads "
+                     f"FETCH_SIZE = {mean('FETCH_SIZE', 'k_stream_copy'):.1f} KiB and WRITE_SIZE = "
+                     f"{mean('WRITE_SIZE', 'k_stream_copy'):.1f} KiB per dispatch: scales "
+                     f"{scale['FETCH_SIZE']:.4f} and {scale['WRITE_SIZE']:.4f}.")
+        kv = [f"kernel: {label}", f"lattice: {'x'.join(map(str, dims))}", f"fetch_kib_per_launch: {f:.1f}",
+              f"write_kib_per_launch: {w:.1f}", f"fetch_scale: {scale['FETCH_SIZE']:.4f}",
+              f"write_scale: {scale['WRITE_SIZE']:.4f}", f"fetch_scaled_bytes_per_launch: {fetch_scaled:.0f}"]
+        if rdreq_dir and kname in reads.get("TCC_EA0_RDREQ_sum", {}):
+            rd, rest = exact_reads(kname)
+            n = {b: mean(f"TCC_EA0_RDREQ_{b}B_sum", kname) for b in (32, 64, 128)}
+            lines.append(f"# Reads by request size (exact): the copy's {copy_rd / 1024:.1f} KiB (unaccounted "
+                         f"requests {copy_rest:.0f}); this kernel 32 B x {n[32]:.0f} + 64 B x {n[64]:.0f} + "
+                         f"128 B x {n[128]:.0f} = {rd:.0f} B (unaccounted {rest:.0f}), against "
+                         f"{fetch_scaled:.0f} B from the scaled FETCH_SIZE.")
+            kv += [f"read_requests_32B_64B_128B: {n[32]:.0f} {n[64]:.0f} {n[128]:.0f}",
+                   f"read_bytes_per_launch: {rd:.0f}"]
+            traffic = rd + write_b
+        else:
+            traffic = fetch_scaled + write_b
         alg = bps * V
-        lines = [
-            f"# HBM traffic of {label} on {'x'.join(map(str, dims))} (one launch = {V} sites)",
-            f"# kernel: {kname}",
-            "# Commands (R = repository root on the GPU box):",
-            "#   " + src.format(c="FETCH_SIZE"),
-            "#   " + src.format(c="WRITE_SIZE"),
-            f"#   python3 bench.py --summarize-traffic $R/gpurun_out/pmc_FETCH_SIZE $R/gpurun_out/pmc_WRITE_SIZE",
-            f"# Calibration, same runs: the 8 GiB streaming copy k_stream_copy reads FETCH_SIZE = "
-            f"{float(np.mean(reads['FETCH_SIZE']['k_stream_copy'])):.1f} KiB and WRITE_SIZE = "
-            f"{float(np.mean(reads['WRITE_SIZE']['k_stream_copy'])):.1f} KiB per dispatch for {copy_kib:.0f} KiB",
-            f"# each, so FETCH_SIZE is scaled by {scale['FETCH_SIZE']:.4f} and WRITE_SIZE by {scale['WRITE_SIZE']:.4f}.",
-            f"# Both count L2 misses: a miss served by the 256 MiB Infinity Cache counts as well.",
-            f"#   traffic {traffic:.0f} B  algorithmic {alg} B  ratio {traffic / alg:.3f}",
-            f"kernel: {label}",
-            f"lattice: {'x'.join(map(str, dims))}",
-            f"fetch_kib_per_launch: {f:.1f}",
-            f"write_kib_per_launch: {w:.1f}",
-            f"fetch_scale: {scale['FETCH_SIZE']:.4f}",
-            f"write_scale: {scale['WRITE_SIZE']:.4f}",
-            f"traffic_bytes_per_launch: {traffic:.0f}",
-            f"algorithmic_bytes_per_launch: {alg}",
-            f"source_sha: {kernel_source_sha()}",
-        ]
+        lines.append("# All of these count L2 misses: a miss served by the 256 MiB Infinity Cache counts as well.")
+        lines.append(f"#   traffic {traffic:.0f} B  algorithmic {alg} B  ratio {traffic / alg:.3f}")
+        kv += [f"traffic_bytes_per_launch: {traffic:.0f}", f"algorithmic_bytes_per_launch: {alg}",
+               f"source_sha: {kernel_source_sha()}"]
         path = os.path.join(PROFILES, f"traffic_{label}_{'x'.join(map(str, dims))}.txt")
         with open(path, "w") as fh:
-            fh.write("\n".join(lines) + "\n")
+            fh.write("\n".join(lines + kv) + "\n")
         print(f"{label}: traffic / algorithmic = {traffic / alg:.3f} -> {os.path.relpath(path, ROOT)}")
 
 
@@ -781,6 +811,8 @@ def main():
         summarize_trace(args.summarize_trace)
         return
     if args.summarize_traffic:
+        if len(args.summarize_traffic) not in (2, 3):
+            raise SystemExit("--summarize-traffic takes FETCH_DIR WRITE_DIR [RDREQ_DIR]")
         summarize_traffic(*args.summarize_traffic)
         return
     dims = tuple(int(v) for v in args.dims.split(","))
