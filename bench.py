@@ -8,10 +8,13 @@ Workload: 32^3 x 64 periodic lattice, links exp(i 0.3 H) (H a Gaussian
 combination of Gell-Mann matrices), m = 0.02, one Gaussian complex128
 source; solve D^+D x = D^+b to a true relative residual of 1e-10.
 A step is one complete solve with the mixed-precision reliable-update CG
-(FP32 arithmetic on 16-bit or FP32 storage, FP64 reliable updates every 50
-iterations), inputs resident in HBM. The same solve in plain FP64 CG is timed
-beside it. The roofline object is the packed Wilson stencil in the inner
-storage precision, timed with HIP events on its own stream.
+(FP32 arithmetic on int8, FP16, BF16 or FP32 storage, FP64 reliable updates
+every 50 iterations; the fastest storage is the headline), inputs resident in
+HBM. The same solve in plain FP64 CG is timed beside it. The roofline object
+is the dominant kernel of the inner loop, timed with HIP events on the
+solver's stream, against 8 TB/s and the measured streaming ceilings. Other
+rows: the standalone D^+, the gauge force, the batched, differentiable,
+Laplacian and out-of-core solves, and the CPU oracle.
 
 Prints one JSON line.
 """
