@@ -136,6 +136,8 @@ def parse():
                     help="skip the force, batched, autograd and Laplacian measurements")
     ap.add_argument("--other-rows", default="force,batched,autograd,laplace,ooc",
                     help="comma-separated subset of the other rows to measure")
+    ap.add_argument("--batched-schedules", default="persistent,lockstep",
+                    help="schedules of the batched row (comma-separated subset of persistent,lockstep)")
     ap.add_argument("--cpu-sample-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--cpu-plan", action="store_true",
                     help="time the FP64 oracle on the host (per D and per CG iteration on the five workloads, full "
@@ -146,6 +148,8 @@ def parse():
     ap.add_argument("--summarize-traffic", nargs="+", default=None, metavar="DIR",
                     help="write profiles/traffic_*.txt from rocprofv3 --pmc runs of this benchmark: FETCH_SIZE, "
                          "WRITE_SIZE and (optional third directory) RDREQ_COUNTERS, the read requests by size")
+    ap.add_argument("--summarize-batched", nargs=3, default=None, metavar=("ISSUE_DIR", "RDREQ_DIR", "WRITE_DIR"),
+                    help="write profiles/batched_counters_*.md from three rocprofv3 --pmc runs of the batched row")
     ap.add_argument("--summarize-issue", default=None, metavar="DIR",
                     help="write profiles/issue_hot_kernels_*.md from one rocprofv3 --pmc run of this benchmark "
                          "with ISSUE_COUNTERS (instruction mix and VALU issue time per kernel)")
@@ -294,7 +298,7 @@ def batched_rhs_bytes(inner):
 FORCE_BYTES = 2 * 192 + 4 * 9 * 16
 
 
-def bench_batched(dev):
+def bench_batched(dev, schedules=("persistent", "lockstep")):
     """16 systems sharing one gauge field, for each schedule and inner storage
     (persistent: one cooperative launch; lockstep: one launch per CG step over
     all systems); the row reports the fastest and lists all."""
@@ -307,8 +311,8 @@ def bench_batched(dev):
     pts = fieldgen.point_sources(dims)[:12]
     gs = fieldgen.gaussian_spinor(dims, 200105249, nrhs=4)
     B = torch.from_numpy(np.concatenate([pts, gs]).astype(np.complex64)).to(dev)
-    combos = [("persistent", inner) for inner in ("f32", "f16", "bf16", "i8")] + \
-             [("lockstep", inner) for inner in ("f16", "bf16", "i8")]
+    combos = [("persistent", inner) for inner in ("f32", "f16", "bf16", "i8") if "persistent" in schedules] + \
+             [("lockstep", inner) for inner in ("f16", "bf16", "i8") if "lockstep" in schedules]
     need = 0
     for sched, inner in combos:
         p, _ = wd.ops.make_params(TOL, 20000, inner, 50, "source", wd._lib.WD_C64, True, 0, schedule=sched)
@@ -805,10 +809,92 @@ def summarize_issue(directory, dims=DIMS):
     print("\n".join(lines))
 
 
+# kernels of the lockstep batch, compared per grid size: one system of
+# 24^3 x 48 (the sixteen single solves) against all sixteen in one launch
+BATCHED_KERNELS = {
+    "FP16 D": ("k_wilson_tiled<3, true, false>", BATCHED_VEC_B["f16"] * 2 + 96),
+    "FP16 r update": ("k_cg_update_tiled<3, true>", BATCHED_VEC_B["f16"] * 3 + 96),
+    "int8 D": ("k_wilson_tiled<4, true, false>", BATCHED_VEC_B["i8"] * 2 + 96),
+    "int8 r update": ("k_cg_update_tiled<4, true>", BATCHED_VEC_B["i8"] * 3 + 96),
+    "FP64 D (reliable update)": ("k_wilson_packed<0, false, true>", 960),
+}
+
+
+def summarize_batched(issue_dir, rdreq_dir, write_dir, dims=BATCHED_DIMS, nrhs=16):
+    """Per grid size (one system or all nrhs in one launch) of the batched
+    row's kernels: time, VALU instructions and VALU issue share, and the
+    exact memory bytes per site and system (read requests by size, WRITE_SIZE)."""
+    import csv
+    import glob
+    V = int(np.prod(dims))
+    agent = {}
+    for path in glob.glob(os.path.join(issue_dir, "**", "*agent_info.csv"), recursive=True):
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r.get("Agent_Type") == "GPU":
+                    agent = r
+    simds = int(agent.get("Simd_Count", 1024))
+    xcds = int(agent.get("Num_Xcc", 8))
+    val, dur = {}, {}
+    for directory in (issue_dir, rdreq_dir, write_dir):
+        for r in _rocprof_rows(directory, "counter_collection.csv"):
+            key = (_short_name(r["Kernel_Name"]), int(r["Grid_Size"]))
+            val.setdefault(key, {}).setdefault(r["Counter_Name"], {})[(directory, r["Dispatch_Id"])] = \
+                float(r["Counter_Value"])
+            if directory == issue_dir:
+                dur.setdefault(key, {})[r["Dispatch_Id"]] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+
+    def mean_working(key, counter):
+        # means over the launches that did work (by duration in the issue pass,
+        # by value in the others: a closed gate moves no data)
+        c = val[key][counter]
+        v = list(c.values())
+        return float(np.mean(_working(v))) if counter != "SQ_WAVES" else float(np.mean([x for x in v if x > 0]))
+
+    lines = [f"# Batched kernels on {'x'.join(map(str, dims))}: one system per launch against {nrhs} systems per",
+             "# launch (lockstep), from three rocprofv3 --pmc passes of the batched row (lockstep schedule and the",
+             "# sixteen single solves; the persistent kernel is not profiled here).",
+             "# Commands (R = repository root on the GPU box):"]
+    cmd = ("cd /tmp && TMPDIR=/tmp timeout -s KILL 300 rocprofv3 --pmc {c} -d $R/gpurun_out/pmc_batched_{d} -o p "
+           "--output-format csv -- python3 $R/bench.py --steps 1 --warmup 1 --fp64-steps 1 --dslash-reps 5 "
+           "--no-cpu-baseline --other-rows batched --batched-schedules lockstep")
+    lines += ["#   " + cmd.format(c=ISSUE_COUNTERS, d="issue"), "#   " + cmd.format(c=RDREQ_COUNTERS, d="rdreq"),
+              "#   " + cmd.format(c="WRITE_SIZE", d="write"),
+              "#   python3 bench.py --summarize-batched $R/gpurun_out/pmc_batched_issue "
+              "$R/gpurun_out/pmc_batched_rdreq $R/gpurun_out/pmc_batched_write",
+              "# bytes per site and system: exact reads (32/64/128-byte requests) and WRITE_SIZE; algorithmic",
+              "# bytes per site and system count the two-row links once per system.",
+              f"# source_sha: {kernel_source_sha()}", "#",
+              "kernel | systems per launch | us per system | VALU/wave | VALU-issue | read B/site/system | "
+              "write B/site/system | algorithmic B/site/system"]
+    for label, (kname, bps) in BATCHED_KERNELS.items():
+        for n, grid in ((1, V), (nrhs, V * nrhs)):
+            key = (kname, grid)
+            if key not in val or "SQ_INSTS_VALU" not in val[key] or "WRITE_SIZE" not in val[key]:
+                continue
+            d = _working(list(dur[key].values()))
+            us = float(np.mean(d)) / 1e3
+            cycles = mean_working(key, "GRBM_GUI_ACTIVE") / xcds
+            waves = mean_working(key, "SQ_WAVES")
+            vpw = mean_working(key, "SQ_INSTS_VALU") / waves
+            issue = mean_working(key, "SQ_INSTS_VALU") * 4 / simds / cycles
+            rd = sum(b * mean_working(key, f"TCC_EA0_RDREQ_{b}B_sum") for b in (32, 64, 128))
+            wr = mean_working(key, "WRITE_SIZE") * 1024
+            lines.append(f"{label} | {n} | {us / n:.1f} | {vpw:.0f} | {issue:.2f} | {rd / (V * n):.0f} | "
+                         f"{wr / (V * n):.0f} | {bps}")
+    path = os.path.join(PROFILES, f"batched_counters_{'x'.join(map(str, dims))}.md")
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     args = parse()
     if args.summarize_issue:
         summarize_issue(args.summarize_issue)
+        return
+    if args.summarize_batched:
+        summarize_batched(*args.summarize_batched)
         return
     if args.summarize_trace:
         summarize_trace(args.summarize_trace)
@@ -995,7 +1081,7 @@ def main():
         if "force" in rows:
             other["force_32x32x32x64"] = bench_force(dev, bt, x64)
         if "batched" in rows:
-            other["batched_cg"] = bench_batched(dev)
+            other["batched_cg"] = bench_batched(dev, tuple(args.batched_schedules.split(",")))
         if "autograd" in rows:
             other["autograd_solve"] = bench_autograd(dev)
         if "laplace" in rows:
