@@ -680,14 +680,14 @@ def summarize_traffic(fetch_dir, write_dir, rdreq_dir=None, dims=DIMS):
         return 32 * n32 + 64 * n64 + 128 * n128, mean("TCC_EA0_RDREQ_sum", kname) - (n32 + n64 + n128)
 
     scale = {c: copy_kib / mean(c, "k_stream_copy") for c in ("FETCH_SIZE", "WRITE_SIZE")}
-    cmd = "cd /tmp && TMPDIR=/tmp timeout -s KILL 300 rocprofv3 --pmc {c} -d $R/gpurun_out/pmc_{d} -o p " \
+    cmd = "cd /tmp && TMPDIR=/tmp timeout -s KILL 300 rocprofv3 --pmc {c} -d $OUT/pmc_{d} -o p " \
           "--output-format csv -- python3 $R/bench.py --steps 1 --warmup 1 --inner i8 --fp64-steps 1 " \
           "--dslash-reps 20 --no-cpu-baseline --other-rows force"
     cmds = [cmd.format(c="FETCH_SIZE", d="FETCH_SIZE"), cmd.format(c="WRITE_SIZE", d="WRITE_SIZE")]
-    summ = "python3 bench.py --summarize-traffic $R/gpurun_out/pmc_FETCH_SIZE $R/gpurun_out/pmc_WRITE_SIZE"
+    summ = "python3 bench.py --summarize-traffic $OUT/pmc_FETCH_SIZE $OUT/pmc_WRITE_SIZE"
     if rdreq_dir:
         cmds.append(cmd.format(c=RDREQ_COUNTERS, d="RDREQ"))
-        summ += " $R/gpurun_out/pmc_RDREQ"
+        summ += " $OUT/pmc_RDREQ"
         copy_rd, copy_rest = exact_reads("k_stream_copy")
     for label, (kname, bps) in TRAFFIC_KERNELS.items():
         if kname not in reads["FETCH_SIZE"] or kname not in reads["WRITE_SIZE"]:
@@ -697,7 +697,7 @@ def summarize_traffic(fetch_dir, write_dir, rdreq_dir=None, dims=DIMS):
         fetch_scaled = f * scale["FETCH_SIZE"] * 1024
         write_b = w * scale["WRITE_SIZE"] * 1024
         lines = [f"# Memory traffic of {label} on {'x'.join(map(str, dims))} (one launch = {V} sites)",
-                 f"# kernel: {kname}", "# Commands (R = repository root on the GPU box):"]
+                 f"# kernel: {kname}", "# Commands (R = repository root, OUT = an output directory):"]
         lines += ["#   " + c for c in cmds] + ["#   " + summ]
         lines.append(f"# The 8 GiB streaming copy k_stream_copy (reads = writes = {copy_kib:.0f} KiB) reads "
                      f"FETCH_SIZE = {mean('FETCH_SIZE', 'k_stream_copy'):.1f} KiB and WRITE_SIZE = "
@@ -765,13 +765,13 @@ def summarize_issue(directory, dims=DIMS):
     kernels = dict(TRAFFIC_KERNELS)
     kernels["k_p_update_i8"] = ("k_p_update_ring<4>", loop_kernel_bytes("i8", True)["p_update"])
     cmd = ("cd /tmp && TMPDIR=/tmp timeout -s KILL 300 rocprofv3 --pmc " + ISSUE_COUNTERS +
-           " -d $R/gpurun_out/pmc_issue -o p --output-format csv -- python3 $R/bench.py --steps 1 --warmup 1 "
+           " -d $OUT/pmc_issue -o p --output-format csv -- python3 $R/bench.py --steps 1 --warmup 1 "
            "--inner i8 --fp64-steps 1 --dslash-reps 20 --no-cpu-baseline --other-rows force")
     lines = [
         f"# Instruction mix and VALU issue time of the hot kernels on {'x'.join(map(str, dims))} (one MI355X)",
-        "# Commands (R = repository root on the GPU box):",
+        "# Commands (R = repository root, OUT = an output directory):",
         "#   " + cmd,
-        "#   python3 bench.py --summarize-issue $R/gpurun_out/pmc_issue",
+        "#   python3 bench.py --summarize-issue $OUT/pmc_issue",
         f"# Agent: {simds} SIMDs, {xcds} XCDs. Per-wave figures are per wave64 (one site per lane).",
         "# cycles = GRBM_GUI_ACTIVE / XCDs (the dispatch's length at the clock it ran; clock = cycles / time);",
         "# VALU-issue = SQ_INSTS_VALU x 4 / SIMDs / cycles: the share of the dispatch's cycles that its VALU",
@@ -854,14 +854,14 @@ def summarize_batched(issue_dir, rdreq_dir, write_dir, dims=BATCHED_DIMS, nrhs=1
     lines = [f"# Batched kernels on {'x'.join(map(str, dims))}: one system per launch against {nrhs} systems per",
              "# launch (lockstep), from three rocprofv3 --pmc passes of the batched row (lockstep schedule and the",
              "# sixteen single solves; the persistent kernel is not profiled here).",
-             "# Commands (R = repository root on the GPU box):"]
-    cmd = ("cd /tmp && TMPDIR=/tmp timeout -s KILL 300 rocprofv3 --pmc {c} -d $R/gpurun_out/pmc_batched_{d} -o p "
+             "# Commands (R = repository root, OUT = an output directory):"]
+    cmd = ("cd /tmp && TMPDIR=/tmp timeout -s KILL 300 rocprofv3 --pmc {c} -d $OUT/pmc_batched_{d} -o p "
            "--output-format csv -- python3 $R/bench.py --steps 1 --warmup 1 --fp64-steps 1 --dslash-reps 5 "
            "--no-cpu-baseline --other-rows batched --batched-schedules lockstep")
     lines += ["#   " + cmd.format(c=ISSUE_COUNTERS, d="issue"), "#   " + cmd.format(c=RDREQ_COUNTERS, d="rdreq"),
               "#   " + cmd.format(c="WRITE_SIZE", d="write"),
-              "#   python3 bench.py --summarize-batched $R/gpurun_out/pmc_batched_issue "
-              "$R/gpurun_out/pmc_batched_rdreq $R/gpurun_out/pmc_batched_write",
+              "#   python3 bench.py --summarize-batched $OUT/pmc_batched_issue "
+              "$OUT/pmc_batched_rdreq $OUT/pmc_batched_write",
               "# bytes per site and system: exact reads (32/64/128-byte requests) and WRITE_SIZE; algorithmic",
               "# bytes per site and system count the two-row links once per system.",
               f"# source_sha: {kernel_source_sha()}", "#",
