@@ -357,7 +357,23 @@ def bench_batched(dev, schedules=("persistent", "lockstep")):
     return out
 
 
-def bench_force(dev, a, b, reps=20):
+def warm_up(fn, seconds=0.1):
+    """Launch fn in batches of 10 until `seconds` of back-to-back GPU work have
+    run. The clock takes a few tens of milliseconds of sustained load to reach
+    its working level (the force kernel on 32^3x64 goes from ~540 to ~465 us per
+    launch over its first ~60 launches, and back after an idle pause), so a
+    short burst of launches is timed below its steady rate."""
+    import torch
+    t0 = time.perf_counter()
+    while True:
+        for _ in range(10):
+            fn()
+        torch.cuda.current_stream().synchronize()
+        if time.perf_counter() - t0 >= seconds:
+            return
+
+
+def bench_force(dev, a, b, reps=50):
     """G(a, b) on the benchmark lattice (FP64, canonical layout), HIP events on one stream."""
     import torch
     import paper_2001_05218_amd as wd
@@ -366,6 +382,7 @@ def bench_force(dev, a, b, reps=20):
     stream = torch.cuda.Stream(dev)
     with torch.cuda.stream(stream):
         F = wd.wilson_force(a, b)
+        warm_up(lambda: wd.wilson_force(a, b, out=F))
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -1036,8 +1053,7 @@ def main():
             Up = wd.pack_gauge(Ut, prec)
             pin = wd.pack_spinor(bt, prec)
             pout = wd.empty_packed_spinor(dims, prec, dev)
-            for _ in range(10):
-                wd.wilson_apply_packed(Up, pin, pout, dims, MASS, prec, True)
+            warm_up(lambda: wd.wilson_apply_packed(Up, pin, pout, dims, MASS, prec, True))
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)

@@ -13,7 +13,12 @@ pytestmark = pytest.mark.gpu
 wd = pytest.importorskip("paper_2001_05218_amd")
 
 
-@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (4, 4, 4, 4), (5, 3, 7, 4), (16, 16, 16, 32)])
+# (8, 8, 8, 16), (8, 16, 24, 4), (4, 16, 8, 2) and (16, 16, 16, 32) take the
+# XCD block order (xy-planes of whole 64-site blocks, Lz a multiple of 8) with
+# one or several blocks per plane and z-planes per XCD; the others run in
+# linear order, with a ragged last block where V is not a multiple of 64.
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (4, 4, 4, 4), (5, 3, 7, 4), (8, 8, 8, 16), (8, 16, 24, 4),
+                                  (4, 16, 8, 2), (16, 16, 16, 32)])
 def test_force_kernel_parity(dims):
     log(f"force dims={dims}")
     a = fieldgen.gaussian_spinor(dims, 1)
@@ -24,8 +29,8 @@ def test_force_kernel_parity(dims):
     assert np.abs(F - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
-def test_force_coeff_and_accumulate():
-    dims = (4, 2, 2, 6)
+@pytest.mark.parametrize("dims", [(4, 2, 2, 6), (8, 8, 16, 2)])
+def test_force_coeff_and_accumulate(dims):
     a, b, c = (fieldgen.gaussian_spinor(dims, s) for s in (3, 4, 5))
     out = wd.wilson_force(to_dev(a), to_dev(b), 2.5)
     wd.wilson_force(to_dev(c), to_dev(a), -0.5, out=out, accumulate=True)

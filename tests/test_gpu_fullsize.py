@@ -16,6 +16,9 @@ lattice.
   (each real component is rounded to nearest, |D| <= m + 8 for unitary links).
 * The Laplacian at 32x32x32x64 (m2 = 0.05): the operator at sampled sites and
   the CG solution over the whole lattice.
+* The gauge force G(a, b) at 32x32x32x64 (the grid and block order the
+  benchmark times), every link of every site against the oracle, written and
+  then accumulated.
 """
 import numpy as np
 import pytest
@@ -93,6 +96,20 @@ def test_wilson_apply_sampled_sites(links):
         ref = oracle.wilson_D_sites(links, psi, MASS, sites, dagger=dag)
         got = np.array([out[t, z, y, x] for (x, y, z, t) in sites])
         assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_force_whole_lattice():
+    log("force 32^3x64 whole lattice")
+    a = fieldgen.gaussian_spinor(DIMS, 200105241)
+    b = fieldgen.gaussian_spinor(DIMS, 200105242)
+    at, bt = to_dev(a), to_dev(b)
+    F = wd.wilson_force(at, bt, 1.0)
+    ref = oracle.force_G(a, b)
+    scale = np.abs(ref).max()
+    assert np.abs(to_np(F) - ref).max() <= 1e-13 * scale
+    wd.wilson_force(bt, at, -0.5, out=F, accumulate=True)
+    ref -= 0.5 * oracle.force_G(b, a)
+    assert np.abs(to_np(F) - ref).max() <= 1e-13 * scale
 
 
 # ---------------------------------------------------------------- batched (c3)
