@@ -90,14 +90,41 @@ KERNEL_SOURCES = ("csrc/wd_kernels.hip", "csrc/wd_common.hpp", "csrc/wd_dslash.h
                   "csrc/wd_reduce.hpp", "csrc/wd_tiled.hpp", "../include/wilson.h")
 
 
+def strip_c_comments(text: str) -> str:
+    """C/C++ source without its comments, each whitespace run as one space
+    (string and character literals kept as written)."""
+    out = []
+    i, n = 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            out.append(" ")
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_source_sha() -> str:
-    """SHA-256 over the sources the stored kernels are compiled from: a stored
-    counter figure is only valid for the kernels it was measured on."""
+    """SHA-256 over the sources the stored kernels are compiled from, comments
+    and layout left out: a stored counter figure is only valid for the kernels
+    it was measured on, and a comment does not change a kernel."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.normpath(os.path.join(CSRC, "..", rel)), "rb") as f:
+        with open(os.path.normpath(os.path.join(CSRC, "..", rel)), encoding="utf-8") as f:
             h.update(os.path.basename(rel).encode())
-            h.update(f.read())
+            h.update(strip_c_comments(f.read()).encode())
     return h.hexdigest()
 
 

@@ -829,12 +829,13 @@ __device__ __forceinline__ void force_wave(const Geom& g, const double2* lds, do
 // Workgroup -> block of 64 sites. Workgroups are dealt round-robin to the 8
 // XCDs. When an xy-plane is a whole number of blocks and Lz a multiple of 8,
 // XCD k takes the z-planes [k Lz/8, (k+1) Lz/8) of every t-plane and walks
-// them xy-block fastest, then z, then t: a block's y neighbours are the next
-// block of the same XCD, its z neighbours Lx Ly / 64 blocks later, its t
-// neighbours one slice (Lx Ly Lz / 512 blocks) later, all still in that XCD's
-// L2 (in linear order the y neighbours of half the sites were on another XCD
-// and the t neighbours 64 of its blocks away: 1.78 against 1.27 fetches of each
-// record on 32^3 x 64). Otherwise blocks run in linear order.
+// them xy-block fastest, then z, then t: a block's y neighbours are in the
+// same XCD's next block, its z neighbours Lx Ly / 64 of its blocks later (on
+// the next XCD for the last of its z-planes), its t neighbours Lx Ly Lz / 512
+// of its blocks later. In linear order the y neighbours of a block's second
+// x-row lay in the next block, on another XCD: each a and b record was fetched
+// 1.78 times on 32^3 x 64, against 1.27 in this order. Otherwise blocks run in
+// linear order.
 __device__ __forceinline__ int force_block(const Geom& g, int b, int zsplit) {
   if (!zsplit) return b;
   const int cp = g.stride[2] / kForceSites;   // blocks per xy-plane

@@ -113,3 +113,23 @@ def test_trace_summary_per_grid(tmp_path, capsys):
     out = capsys.readouterr().out.splitlines()
     assert "k_cg_update_tiled<4, true> | grid 663552 | 6 | 5 | 30.0" in out   # a gated 3 us launch left out
     assert "k_cg_update_tiled<4, true> | grid 10616832 | 5 | 5 | 400.0" in out
+
+
+def test_source_sha_ignores_comments_only(tmp_path, monkeypatch):
+    assert bench.strip_c_comments('int a; // x "y"\n/* z\n */ const char* s = "//k /*"; char c = \'/\';') == \
+        'int a; const char* s = "//k /*"; char c = \'/\';'
+    src = os.path.normpath(os.path.join(bench.CSRC, ".."))
+    pkg = tmp_path / "pkg"
+    (pkg / "csrc").mkdir(parents=True)
+    (tmp_path / "include").mkdir()
+    for rel in bench.KERNEL_SOURCES:
+        text = open(os.path.normpath(os.path.join(src, rel)), encoding="utf-8").read()
+        open(os.path.normpath(os.path.join(pkg, rel)), "w", encoding="utf-8").write(text)
+    monkeypatch.setattr(bench, "CSRC", str(pkg / "csrc"))
+    base = bench.kernel_source_sha()
+    k = pkg / "csrc" / "wd_kernels.hip"
+    text = k.read_text(encoding="utf-8")
+    k.write_text("// a new comment\n" + text.replace("\n", "  \n", 3), encoding="utf-8")
+    assert bench.kernel_source_sha() == base
+    k.write_text(text.replace("kForceSites = 64", "kForceSites = 32"), encoding="utf-8")
+    assert bench.kernel_source_sha() != base
