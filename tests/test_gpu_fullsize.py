@@ -19,6 +19,8 @@ lattice.
 * The gauge force G(a, b) at 32x32x32x64 (the grid and block order the
   benchmark times), every link of every site against the oracle, written and
   then accumulated.
+* The packed D^+ of the benchmark's Dslash loop in every storage (and the
+  solver's two-row link formats) at 64 sampled sites of 32x32x32x64.
 """
 import numpy as np
 import pytest
@@ -110,6 +112,28 @@ def test_force_whole_lattice():
     wd.wilson_force(bt, at, -0.5, out=F, accumulate=True)
     ref -= 0.5 * oracle.force_G(b, a)
     assert np.abs(to_np(F) - ref).max() <= 1e-13 * scale
+
+
+# the benchmark's D^+ loop: each storage as bench.py packs and launches it;
+# bounds as for the same kernels on small lattices (relative over the sample)
+@pytest.mark.parametrize("prec,bound", [("f64", 1e-12), ("f32", 2e-6), ("bf16", 1.5e-2), ("f16", 3e-3),
+                                        ("i8", 2e-2), ("f16_rows2", 3e-3), ("i8_rows2", 2e-2)])
+def test_packed_dagger_sampled_sites(links, source, prec, bound):
+    log(f"packed D^+ 32^3x64 {prec}")
+    b = source[0]
+    Ut, bt = to_dev(links), to_dev(b)
+    Up = wd.pack_gauge(Ut, prec)
+    pin = wd.pack_spinor(bt, prec)
+    pout = wd.empty_packed_spinor(DIMS, prec, bt.device)
+    wd.wilson_apply_packed(Up, pin, pout, DIMS, MASS, prec, True)
+    out = to_np(wd.unpack_spinor(pout, DIMS, prec))
+    sites = _sites(64, 15)
+    ref = oracle.wilson_D_sites(links, b, MASS, sites, dagger=True)
+    got = np.array([out[t, z, y, x] for (x, y, z, t) in sites])
+    assert np.linalg.norm(got - ref) <= bound * np.linalg.norm(ref)
+    if prec == "f64":
+        for k in range(len(sites)):
+            assert np.abs(got[k] - ref[k]).max() <= 1e-12 * np.abs(ref[k]).max()
 
 
 # ---------------------------------------------------------------- batched (c3)
