@@ -266,3 +266,14 @@ def test_stream_rejects_bad_args(lib):
     assert lib.wd_stream(0, p16 + 8, p16, 16, None) == _lib.WD_ERR_INVALID    # misaligned
     assert lib.wd_stream(0, None, p16, 16, None) == _lib.WD_ERR_INVALID       # NULL
     assert lib.wd_stream_partials(1 << 33) >= 1
+
+
+def test_largest_lattice_accepted_and_one_plane_more_rejected(lib):
+    # 2^28 sites is the largest volume the library takes (its kernels index
+    # sites in 32-bit integers and fields in 64-bit offsets); sizes only, no
+    # device memory touched
+    p = ctypes.byref(_params())
+    at_max = lib.wd_workspace_bytes(_lat((128, 128, 128, 128)), p, 1)
+    assert at_max >= 128 ** 4 * (4 * 9 * 16 + 5 * 12 * 16)   # FP64 links and five FP64 vectors at least
+    assert lib.wd_workspace_bytes(_lat((128, 128, 128, 130)), p, 1) == 0
+    assert "exceeds 2^28" in _lib.last_error()
