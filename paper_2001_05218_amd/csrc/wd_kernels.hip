@@ -715,7 +715,8 @@ __global__ __launch_bounds__(kBlock) void k_norm2(Geom g, SpinorBuf v, int gate,
 //   sum_spin ((1-g)a)_s (x) b_s^* = h (x) (b_up - A b_dn)^*  (two colour outer products),
 // and likewise (1 + g): sum_spin b_s (x) ((1+g)a)_s^* = (b_up + A b_dn) (x) h'^*.
 
-// f += sum_{k=0,1} u[k] (x) conj(v[k]) for half spinors u, v (index (k * 3 + c) * 2).
+// f += sum_{k=0,1} u[k] (x) conj(v[k]) for half spinors u, v (index (k * 3 + c) * 2),
+// each product added into f by its own FMA (four per complex term)
 __device__ __forceinline__ void outer_acc(const double u[12], const double v[12], double f[18]) {
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -725,8 +726,8 @@ __device__ __forceinline__ void outer_acc(const double u[12], const double v[12]
       for (int k = 0; k < 2; ++k) {
         const double ur = u[(k * 3 + i) * 2], ui = u[(k * 3 + i) * 2 + 1];
         const double vr = v[(k * 3 + j) * 2], vi = v[(k * 3 + j) * 2 + 1];
-        f[(i * 3 + j) * 2] += ur * vr + ui * vi;
-        f[(i * 3 + j) * 2 + 1] += ui * vr - ur * vi;
+        f[(i * 3 + j) * 2] = fma(ur, vr, fma(ui, vi, f[(i * 3 + j) * 2]));
+        f[(i * 3 + j) * 2 + 1] = fma(ui, vr, fma(-ur, vi, f[(i * 3 + j) * 2 + 1]));
       }
     }
   }
